@@ -1,0 +1,258 @@
+/*
+ * swsph.h -- C ABI of the MI355X (gfx950) SPH neighbour-loop library.
+ *
+ * The library computes, for particles in periodic cubic boxes, the three
+ * neighbour loops that SWIFT offloads to GPUs in "Task-parallelism in SWIFT
+ * for heterogeneous compute architectures" (Nasar et al.), Section 2.1:
+ *
+ *   density   number density n_i = sum_j W(r_ij, h_i) and dn_i/dh
+ *             (Sec. 2.1.2, Eq. 5-6), mass density rho_i = sum_j m_j W_ij
+ *             (Eq. 2) and drho_i/dh, the smoothing length h_i solved by
+ *             Newton iteration on h^3 n(h) = eta^3 (Sec. 2.1.2), div v and
+ *             curl v (Eq. 3-4), the grad-h factor f_i (Eq. 8, applied as
+ *             1/Omega) and the neighbour count;
+ *   gradient  the signal velocity max_j v_sig,ij (Eq. 10-11) and the
+ *             Laplacian of u -- the per-particle inputs of the dissipation
+ *             switches of Sec. 2.1.3 (Eq. 13, Eq. 21);
+ *   force     acceleration and du/dt (Sec. 2.1.4, Eq. 17-18) with the
+ *             pairwise artificial viscosity of Eq. 7 and Eq. 9-11;
+ *
+ * plus the adjoint of density -> force (gradients of a scalar loss on a and
+ * du/dt with respect to positions, velocities, internal energies, masses).
+ *
+ * Kernel: M4 cubic spline with support H = eps*h (Sec. 2.1.1, eps = 2 as in
+ * the paper's tests, Sec. 3.1).  Cells and tasks: the paper splits the box
+ * into cubic cells and runs "self" (one cell) and "pair" (two neighbouring
+ * cells) tasks (Sec. 2.2.2); here particles are binned on the GPU into a
+ * hierarchy of cubic cells (Morton order, counting sort), grouped into
+ * i-tiles, and each tile's task is the list of cells -- its own (self) and
+ * neighbouring ones (pairs) -- found by a recursive cell search, in the
+ * spirit of the paper's sub-task recursion down to cells of width ~H.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions for every entry point
+ *   - Return value: 0 (SWSPH_OK) or a negative swsph_status.  On failure
+ *     swsph_last_error() returns a thread-local message.  No C++ exception
+ *     crosses this boundary.
+ *   - Arrays named "device" are device pointers owned by the caller, one
+ *     element per particle, contiguous, in the caller's (original) particle
+ *     order, of the plan's dtype (float or double) unless stated otherwise.
+ *   - The workspace `ws` is caller-owned device memory of at least
+ *     swsph_workspace_bytes() bytes, 256-byte aligned; it carries the binned
+ *     particles between calls.  The library never allocates device memory
+ *     in these calls and never synchronises the stream, except where stated.
+ *   - Every call enqueues its work on `stream` (a hipStream_t passed as
+ *     void*; NULL = the default stream) and is capturable into a HIP graph.
+ *   - Arguments are validated on the host before any HIP call: a bad
+ *     argument returns SWSPH_E_ARG without touching the device.
+ *   - Conditions only the device can detect (a particle outside its box, a
+ *     support radius reaching half the box, Newton not converging, a
+ *     workspace too small) are latched into a status word in the workspace
+ *     and reported by swsph_read_stats().
+ *   - Calls on one workspace must not overlap (same stream, or ordered).
+ */
+#ifndef SWSPH_H
+#define SWSPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWSPH_VERSION 1
+
+typedef enum swsph_status {
+    SWSPH_OK = 0,
+    SWSPH_E_ARG = -1,       /* invalid argument (host-side check) */
+    SWSPH_E_HIP = -2,       /* a HIP runtime call failed */
+    SWSPH_E_STATE = -3,     /* loop called before swsph_bin / on a mismatched bin */
+    SWSPH_E_CAPACITY = -4,  /* workspace or internal table too small (device) */
+    SWSPH_E_REACH = -5,     /* some support radius reaches half a box (device) */
+    SWSPH_E_NEWTON = -6,    /* some h did not converge (device) */
+    SWSPH_E_DOMAIN = -7     /* a particle lies outside [0, L) (device) */
+} swsph_status;
+
+/* device status bits (swsph_stats.status) */
+#define SWSPH_ST_CAPACITY 0x1u
+#define SWSPH_ST_REACH    0x2u
+#define SWSPH_ST_NEWTON   0x4u
+#define SWSPH_ST_DOMAIN   0x8u
+#define SWSPH_ST_LOOPCAP  0x10u  /* a device loop hit its iteration cap and stopped */
+
+typedef enum swsph_dtype { SWSPH_F32 = 0, SWSPH_F64 = 1 } swsph_dtype;
+
+/* swsph_config.flags */
+#define SWSPH_FIXED_H          0x1u  /* density: use the given h, no Newton */
+#define SWSPH_NO_VISC          0x2u  /* force: viscosity off */
+#define SWSPH_PER_TASK_LAUNCH  0x4u  /* one kernel launch per tile task */
+#define SWSPH_FLAT_LAUNCH      0x8u  /* one launch, one wavefront per task, no queue */
+
+/* Scheme constants and execution options.  swsph_config_default() fills
+ * eta = 1.2348, eps = 2, gamma = 5/3, alpha = 1, beta = 3, h_tol = 2e-6,
+ * h_max_iter = 40, dtype = F32, flags = 0, tile and LDS sizes chosen by the
+ * library (0). */
+typedef struct swsph_config {
+    double eta;          /* resolution: h^3 n(h) = eta^3 */
+    double eps;          /* support radius H = eps * h */
+    double gamma;        /* adiabatic index, P = (gamma-1) rho u */
+    double alpha;        /* viscosity coefficient (constant, Eq. 16 with B = 1) */
+    double beta;         /* signal-velocity coefficient (Eq. 10) */
+    double h_tol;        /* Newton stop: |h^3 n - eta^3| <= h_tol * eta^3 */
+    int32_t h_max_iter;  /* Newton sweeps before SWSPH_ST_NEWTON is latched */
+    int32_t dtype;       /* swsph_dtype of every particle array */
+    uint32_t flags;      /* SWSPH_* flags above */
+    int32_t tile;        /* i-particles per task: 16, 32 or 64 (0: auto) */
+    int32_t lds_cap;     /* staged j-particles per wavefront: 128..1024 (0: auto) */
+    int32_t order;       /* task order: 0 cost-descending, 1 Morton (tile order) */
+    int32_t leaf_max;    /* cell search: refine cells with more particles (0: auto) */
+    int32_t reserved[5];
+} swsph_config;
+
+/* Particle set.  Positions must lie in [0, box_size[b]) of their box b.
+ * box_id (device int32, nullable when n_box == 1) gives each particle's box;
+ * box_size and box_count are HOST arrays of n_box entries (box_count may be
+ * NULL when n_box == 1: then box_count[0] = n).  h (device, nullable) is the
+ * smoothing-length guess for swsph_bin (NULL: estimated from the local
+ * particle density) and, with SWSPH_FIXED_H, the fixed smoothing lengths. */
+typedef struct swsph_particles {
+    int64_t n;
+    const void *x, *y, *z;       /* positions (device) */
+    const void *vx, *vy, *vz;    /* velocities (device) */
+    const void *u;               /* internal energy per unit mass (device) */
+    const void *m;               /* masses (device) */
+    const int32_t* box_id;       /* device, nullable */
+    int32_t n_box;
+    const double* box_size;      /* host [n_box] */
+    const int64_t* box_count;    /* host [n_box], nullable if n_box == 1 */
+    const void* h;               /* device, nullable: guess (or fixed h) */
+} swsph_particles;
+
+/* Density results (device, original order).  swsph_density writes every
+ * non-null pointer; h, rho and f are required.  The gradient, force and
+ * backward calls read h, rho and f from here. */
+typedef struct swsph_density_out {
+    void *h, *rho, *rho_dh, *wcount, *wcount_dh;
+    void *div_v, *curl_x, *curl_y, *curl_z;
+    void *f;                     /* grad-h factor 1/Omega */
+    int32_t* nngb;               /* #{j != i : r_ij^2 < H_i^2} (binary32 predicate) */
+    int32_t* iters;              /* Newton sweeps used (negative: not converged) */
+} swsph_density_out;
+
+typedef struct swsph_gradient_out {
+    void *v_sig;                 /* max(2 c_i, max_j c_i + c_j - beta mu_ij) */
+    void *lap_u;                 /* 2 sum_j (m_j/rho_j)(u_i-u_j) (1/r) dW/dr(r,h_i) */
+} swsph_gradient_out;
+
+typedef struct swsph_force_out {
+    void *ax, *ay, *az, *dudt;
+    int32_t* nint;               /* nullable: #{j != i : r^2 < max(H_i^2, H_j^2)} */
+} swsph_force_out;
+
+/* Loss gradients on the force outputs (device, original order). */
+typedef struct swsph_force_grad {
+    const void *gax, *gay, *gaz; /* dL/da */
+    const void *gdudt;           /* dL/d(du/dt) */
+} swsph_force_grad;
+
+/* Gradients with respect to the inputs (device, original order, written). */
+typedef struct swsph_input_grad {
+    void *gx, *gy, *gz, *gvx, *gvy, *gvz, *gu, *gm;
+} swsph_input_grad;
+
+typedef struct swsph_stats {
+    uint32_t status;             /* SWSPH_ST_* bits latched since the last bin */
+    uint32_t n_tiles;            /* tile tasks of the last bin */
+    uint64_t pairs_tested[4];    /* candidate pairs tested: density sweep, gradient, force, backward */
+    uint64_t pairs_inside[4];    /* pairs inside the support (useful pairs) */
+    uint64_t newton_sweeps;      /* sum over tiles of density sweeps */
+    uint32_t newton_max;         /* largest sweep count of a tile */
+    uint32_t newton_failed;      /* particles whose h did not converge */
+    uint64_t leaves;             /* cells emitted by the task searches */
+    uint64_t restages;           /* density tiles that widened their search */
+    uint64_t reserved[6];
+} swsph_stats;
+
+typedef struct swsph_plan swsph_plan;
+
+/* Library version (SWSPH_VERSION) and the last error message of this thread. */
+int swsph_version(void);
+const char* swsph_last_error(void);
+
+/* Defaults listed at swsph_config. */
+void swsph_config_default(swsph_config* cfg);
+
+/* Create / destroy a host-side plan: a copy of the configuration, the
+ * geometry of the last bin, and cached graphs.  Fails with SWSPH_E_ARG on
+ * out-of-range constants (eta, eps, gamma > 1, alpha >= 0, beta >= 0,
+ * h_tol > 0, tile/lds_cap values).  Destroying frees host memory only. */
+int swsph_plan_create(swsph_plan** out, const swsph_config* cfg);
+int swsph_plan_destroy(swsph_plan* plan);
+
+/* Workspace size in bytes for n particles in n_box boxes with the given
+ * per-box counts (host, may be NULL for one box) and sizes (host).  Pure
+ * host computation. */
+int swsph_workspace_bytes(const swsph_plan* plan, int64_t n, int32_t n_box,
+                          const int64_t* box_count, const double* box_size,
+                          uint64_t* bytes);
+
+/* Bin the particles: per-box Morton key on a 2^k grid of cubic cells, a
+ * device counting sort on that key (stable: equal keys keep input order),
+ * sorted copies of the particle data in the workspace, the cell table, the
+ * i-tiles and the density task list.  Section 2.2 (cells, self and pair
+ * tasks).  Clears the device status word. */
+int swsph_bin(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream);
+
+/* Density loop with Newton iteration on h (Sec. 2.1.2; SWSPH_FIXED_H: at
+ * the given h).  Needs swsph_bin on the same particles first. */
+int swsph_density(swsph_plan* plan, const swsph_particles* p, swsph_density_out* o,
+                  void* ws, void* stream);
+
+/* Gradient loop (Sec. 2.1.3) at the density results d. */
+int swsph_gradient(swsph_plan* plan, const swsph_particles* p,
+                   const swsph_density_out* d, swsph_gradient_out* o, void* ws,
+                   void* stream);
+
+/* Force loop (Sec. 2.1.4, Eq. 17-18 with the viscosity of Eq. 7, 9-11) at
+ * the density results d. */
+int swsph_force(swsph_plan* plan, const swsph_particles* p, const swsph_density_out* d,
+                swsph_force_out* o, void* ws, void* stream);
+
+/* Adjoint of density -> force: given dL/da and dL/d(du/dt), overwrite gi
+ * with dL/dx, dL/dv, dL/du, dL/dm, differentiating through rho, f and h
+ * (h by the implicit function theorem on h^3 n(h) = eta^3).  d must hold
+ * the density results of the same particles (Newton converged); pair
+ * geometry is recomputed, nothing per pair is stored. */
+int swsph_force_backward(swsph_plan* plan, const swsph_particles* p,
+                         const swsph_density_out* d, const swsph_force_grad* g,
+                         swsph_input_grad* gi, void* ws, void* stream);
+
+/* One whole step: bin, density, gradient and force.  With the default
+ * launch mode the three loops run in ONE persistent kernel: wavefronts pull
+ * tile tasks from a device queue, and a box's gradient and force tasks wait
+ * (per-box counters) until that box's density tasks are done.  Any of
+ * go / fo may be NULL to skip that loop. */
+int swsph_step(swsph_plan* plan, const swsph_particles* p, swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream);
+
+/* Copy the device statistics to the host (synchronises the stream).  The
+ * return value is SWSPH_OK, or the first latched device condition as a
+ * negative status (the stats are filled in either case). */
+int swsph_read_stats(swsph_plan* plan, const void* ws, swsph_stats* out, void* stream);
+
+/* Time the candidate tile sizes, LDS capacities and task orders on these
+ * particles (runs bin + step several times, synchronises) and store the
+ * fastest in the plan.  cache_path (nullable) names a text file used to
+ * reuse the choice across processes (key: device, n, n_box, dtype). */
+int swsph_autotune(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream,
+                   const char* cache_path);
+
+/* The tuning the plan will use: tile, lds_cap, order, leaf_max. */
+int swsph_plan_get_tuning(const swsph_plan* plan, int32_t* tile, int32_t* lds_cap,
+                          int32_t* order, int32_t* leaf_max);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWSPH_H */

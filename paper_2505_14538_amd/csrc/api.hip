@@ -1,0 +1,541 @@
+// api.hip -- the extern "C" entry points declared in include/swsph.h.
+//
+// Host side only: argument checks (before any HIP call), workspace layout,
+// per-box geometry, and the order of kernel launches for each call.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+using namespace swsph;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SWSPH_OK;
+    return fail(SWSPH_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr uint64_t ALIGN = 256;
+uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Geometry {
+    int64_t n = 0;
+    int32_t n_box = 0;
+    int32_t tile = 64;
+    int32_t n_tiles = 0;
+    int64_t n_fine = 0, n_pyr = 0;
+    int64_t leaf_cap = 0;
+    int tsz = 4;
+    std::vector<BoxInfo> boxes;
+    Layout lay{};
+};
+
+constexpr int KMAX = 10;               // Morton key: 3 x 10 bits per box
+constexpr int64_t FINE_MAX = int64_t(1) << 29;
+
+// Task-list capacity: 384 cells per tile on average (a tile of a uniform
+// box needs ~30-120).  Overflow latches SWSPH_ST_CAPACITY.
+int64_t leaf_capacity(int32_t n_tiles) { return 384 * (int64_t)n_tiles + 4096; }
+
+int choose_k(int64_t nb) {
+    // finest grid with about one cell per particle or more (8^k <= 8 nb)
+    int k = 0;
+    while (k < KMAX && (int64_t(1) << (3 * (k + 1))) <= 8 * nb) ++k;
+    return k;
+}
+
+int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_count,
+                   const double* box_size, int tile, int tsz) {
+    if (n < 0) return fail(SWSPH_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (n > (int64_t(1) << 26)) return fail(SWSPH_E_ARG, "n too large (max 2^26)");
+    if (n_box < 1) return fail(SWSPH_E_ARG, "n_box must be >= 1");
+    if (!box_size) return fail(SWSPH_E_ARG, "box_size (host array) is required");
+    if (n_box > 1 && !box_count) return fail(SWSPH_E_ARG, "box_count is required when n_box > 1");
+    G.n = n;
+    G.n_box = n_box;
+    G.tile = tile;
+    G.tsz = tsz;
+    G.boxes.assign(n_box, BoxInfo{});
+    int64_t start = 0, fine = 0, pyr = 0, sum = 0;
+    int32_t toff = 0;
+    for (int b = 0; b < n_box; ++b) {
+        const int64_t nb = box_count ? box_count[b] : n;
+        const double L = box_size[b];
+        if (nb < 0) return fail(SWSPH_E_ARG, "box_count[%d] < 0", b);
+        if (!(L > 0) || !std::isfinite(L)) return fail(SWSPH_E_ARG, "box_size[%d] must be > 0", b);
+        BoxInfo& bi = G.boxes[b];
+        bi.L = L;
+        bi.start = start;
+        bi.count = nb;
+        bi.k = choose_k(nb);
+        bi.fine_off = fine;
+        bi.pyr_off = pyr;
+        bi.tile_off = toff;
+        bi.n_tiles = (int32_t)((nb + tile - 1) / tile);
+        start += nb;
+        sum += nb;
+        fine += int64_t(1) << (3 * bi.k);
+        pyr += pyr_level_off(bi.k + 1);
+        toff += bi.n_tiles;
+        if (fine > FINE_MAX) return fail(SWSPH_E_ARG, "too many cells (boxes x grid)");
+    }
+    if (sum != n) return fail(SWSPH_E_ARG, "sum of box_count (%lld) != n (%lld)", (long long)sum,
+                              (long long)n);
+    G.n_fine = fine;
+    G.n_pyr = pyr;
+    G.n_tiles = toff;
+    // layout
+    Layout& l = G.lay;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    const uint64_t N = (uint64_t)n, T = (uint64_t)tsz;
+    l.counters = take(sizeof(Counters));
+    l.boxtab = take(sizeof(BoxInfo) * n_box);
+    l.phase = take(sizeof(uint32_t) * 4 * n_box);
+    l.keys = take(4 * N);
+    l.slot = take(4 * N);
+    l.tmpidx = take(4 * N);
+    l.perm = take(4 * N);
+    l.rank = take(4 * N);
+    l.fine_count = take(4 * (uint64_t)(fine + 1));
+    l.cstart = take(4 * (uint64_t)(fine + 2));
+    l.scan_part = take(4 * (uint64_t)scan_partials_needed(fine + 1));
+    l.pos4 = take(4 * T * N);
+    l.vel4 = take(4 * T * N);
+    l.hs = take(T * N);
+    l.dens4 = take(4 * T * N);
+    l.hmaxpyr = take(4 * (uint64_t)pyr);
+    l.tiles = take(sizeof(Tile) * (uint64_t)toff);
+    l.order = take(4 * (uint64_t)toff);
+    l.leaf_cnt = take(4 * (uint64_t)(toff + 1));
+    l.leaf_off = take(4 * (uint64_t)(toff + 2));
+    l.leaf_part = take(4 * (uint64_t)scan_partials_needed(toff + 1));
+    G.leaf_cap = leaf_capacity(toff);
+    l.leaves = take(8 * (uint64_t)G.leaf_cap);
+    l.trad = take(4 * (uint64_t)toff);
+    l.tflag = take(4 * (uint64_t)toff);
+    l.d_out = take(10 * T * N);
+    l.d_int = take(2 * 4 * N);
+    l.g_out = take(2 * T * N);
+    l.f_out = take(4 * T * N);
+    l.f_int = take(4 * N);
+    l.adj = take(16 * T * N);
+    l.total = o;
+    return SWSPH_OK;
+}
+
+}  // namespace
+
+struct swsph_plan {
+    swsph_config cfg;
+    int32_t tile, lds_cap, order, leaf_max;
+    bool binned = false;
+    void* ws = nullptr;
+    Geometry G;
+    uint64_t bin_id = 0;
+};
+
+namespace {
+
+int check_config(const swsph_config* c) {
+    if (!c) return fail(SWSPH_E_ARG, "config is NULL");
+    if (!(c->eta > 0) || !(c->eps > 0)) return fail(SWSPH_E_ARG, "eta and eps must be > 0");
+    if (!(c->gamma > 1)) return fail(SWSPH_E_ARG, "gamma must be > 1");
+    if (!(c->alpha >= 0) || !(c->beta >= 0)) return fail(SWSPH_E_ARG, "alpha, beta must be >= 0");
+    if (!(c->h_tol > 0) || !(c->h_tol < 0.1)) return fail(SWSPH_E_ARG, "h_tol must be in (0, 0.1)");
+    if (c->h_max_iter < 1 || c->h_max_iter > 1000) return fail(SWSPH_E_ARG, "h_max_iter in [1, 1000]");
+    if (c->dtype != SWSPH_F32 && c->dtype != SWSPH_F64) return fail(SWSPH_E_ARG, "bad dtype");
+    if (c->tile != 0 && c->tile != 16 && c->tile != 32 && c->tile != 64)
+        return fail(SWSPH_E_ARG, "tile must be 0, 16, 32 or 64");
+    if (c->lds_cap != 0 && c->lds_cap != 128 && c->lds_cap != 256 && c->lds_cap != 512)
+        return fail(SWSPH_E_ARG, "lds_cap must be 0, 128, 256 or 512");
+    if (c->order != 0 && c->order != 1) return fail(SWSPH_E_ARG, "order must be 0 or 1");
+    if (c->leaf_max < 0 || c->leaf_max > 4096) return fail(SWSPH_E_ARG, "leaf_max in [0, 4096]");
+    if ((c->flags & SWSPH_PER_TASK_LAUNCH) && (c->flags & SWSPH_FLAT_LAUNCH))
+        return fail(SWSPH_E_ARG, "PER_TASK_LAUNCH and FLAT_LAUNCH are exclusive");
+    return SWSPH_OK;
+}
+
+int check_particles(const swsph_plan* pl, const swsph_particles* p, bool need_u) {
+    if (!p) return fail(SWSPH_E_ARG, "particles is NULL");
+    if (p->n < 0) return fail(SWSPH_E_ARG, "n < 0");
+    if (p->n > 0) {
+        if (!p->x || !p->y || !p->z) return fail(SWSPH_E_ARG, "positions are NULL");
+        if (!p->vx || !p->vy || !p->vz) return fail(SWSPH_E_ARG, "velocities are NULL");
+        if (!p->m) return fail(SWSPH_E_ARG, "masses are NULL");
+        if (need_u && !p->u) return fail(SWSPH_E_ARG, "internal energies are NULL");
+    }
+    if (p->n_box < 1) return fail(SWSPH_E_ARG, "n_box must be >= 1");
+    if (p->n_box > 1 && !p->box_id) return fail(SWSPH_E_ARG, "box_id is required when n_box > 1");
+    if (!p->box_size) return fail(SWSPH_E_ARG, "box_size is NULL");
+    if ((pl->cfg.flags & SWSPH_FIXED_H) && p->n > 0 && !p->h)
+        return fail(SWSPH_E_ARG, "SWSPH_FIXED_H needs particles.h");
+    return SWSPH_OK;
+}
+
+Scheme scheme_of(const swsph_plan* pl) {
+    Scheme s;
+    s.eta = pl->cfg.eta;
+    s.eps = pl->cfg.eps;
+    s.gamma = pl->cfg.gamma;
+    s.alpha = pl->cfg.alpha;
+    s.beta = pl->cfg.beta;
+    s.h_tol = pl->cfg.h_tol;
+    s.h_max_iter = pl->cfg.h_max_iter;
+    s.flags = pl->cfg.flags;
+    s.leaf_max = pl->leaf_max;
+    return s;
+}
+
+BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
+    const Layout& l = pl->G.lay;
+    char* w = (char*)ws;
+    BinPtrs b;
+    b.cnt = (Counters*)(w + l.counters);
+    b.boxtab = (BoxInfo*)(w + l.boxtab);
+    b.phase = (uint32_t*)(w + l.phase);
+    b.keys = (uint32_t*)(w + l.keys);
+    b.slot = (int32_t*)(w + l.slot);
+    b.tmpidx = (int32_t*)(w + l.tmpidx);
+    b.perm = (int32_t*)(w + l.perm);
+    b.rank = (int32_t*)(w + l.rank);
+    b.fine_count = (int32_t*)(w + l.fine_count);
+    b.cstart = (int32_t*)(w + l.cstart);
+    b.scan_part = (int32_t*)(w + l.scan_part);
+    b.pos4 = w + l.pos4;
+    b.vel4 = w + l.vel4;
+    b.hs = w + l.hs;
+    b.dens4 = w + l.dens4;
+    b.hmaxpyr = (float*)(w + l.hmaxpyr);
+    b.tiles = (Tile*)(w + l.tiles);
+    b.order = (int32_t*)(w + l.order);
+    b.leaf_cnt = (int32_t*)(w + l.leaf_cnt);
+    b.leaf_off = (int32_t*)(w + l.leaf_off);
+    b.leaf_part = (int32_t*)(w + l.leaf_part);
+    b.leaves = (int2*)(w + l.leaves);
+    b.leaf_cap = pl->G.leaf_cap;
+    b.trad = (float*)(w + l.trad);
+    b.tflag = (int32_t*)(w + l.tflag);
+    b.d_out = w + l.d_out;
+    b.d_int = (int32_t*)(w + l.d_int);
+    b.g_out = w + l.g_out;
+    b.f_out = w + l.f_out;
+    b.f_int = (int32_t*)(w + l.f_int);
+    b.adj = w + l.adj;
+    b.n = pl->G.n;
+    b.n_box = pl->G.n_box;
+    b.n_tiles = pl->G.n_tiles;
+    b.tile = pl->G.tile;
+    b.n_fine = pl->G.n_fine;
+    b.n_pyr = pl->G.n_pyr;
+    return b;
+}
+
+int mode_of(const swsph_plan* pl) {
+    if (pl->cfg.flags & SWSPH_PER_TASK_LAUNCH) return MODE_PER_TASK;
+    if (pl->cfg.flags & SWSPH_FLAT_LAUNCH) return MODE_FLAT;
+    return MODE_QUEUE;
+}
+
+int check_bound(const swsph_plan* pl, const swsph_particles* p, const void* ws) {
+    if (!pl->binned) return fail(SWSPH_E_STATE, "swsph_bin has not been called on this plan");
+    if (ws != pl->ws) return fail(SWSPH_E_STATE, "workspace differs from the one passed to swsph_bin");
+    if (p->n != pl->G.n || p->n_box != pl->G.n_box)
+        return fail(SWSPH_E_STATE, "particle count / boxes differ from the last swsph_bin");
+    return SWSPH_OK;
+}
+
+template <typename T>
+void unsort_density(const BinPtrs& b, swsph_density_out* o, hipStream_t s) {
+    const int64_t n = b.n;
+    T* d = (T*)b.d_out;
+    void* dst[10] = {o->h, o->rho, o->rho_dh, o->wcount, o->wcount_dh,
+                     o->div_v, o->curl_x, o->curl_y, o->curl_z, o->f};
+    for (int k = 0; k < 10; ++k)
+        if (dst[k]) launch_unsort<T>(n, b.rank, d + k * n, dst[k], s);
+    if (o->nngb) launch_unsort<int32_t>(n, b.rank, b.d_int, o->nngb, s);
+    if (o->iters) launch_unsort<int32_t>(n, b.rank, b.d_int + n, o->iters, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swsph_version(void) { return SWSPH_VERSION; }
+
+const char* swsph_last_error(void) { return g_err.c_str(); }
+
+void swsph_config_default(swsph_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->eta = 1.2348;
+    c->eps = 2.0;
+    c->gamma = 5.0 / 3.0;
+    c->alpha = 1.0;
+    c->beta = 3.0;
+    c->h_tol = 2e-6;
+    c->h_max_iter = 40;
+    c->dtype = SWSPH_F32;
+    c->flags = 0;
+    c->tile = 0;
+    c->lds_cap = 0;
+    c->order = 1;
+    c->leaf_max = 0;
+}
+
+int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
+    if (!out) return fail(SWSPH_E_ARG, "out is NULL");
+    *out = nullptr;
+    int r = check_config(cfg);
+    if (r) return r;
+    swsph_plan* pl = new (std::nothrow) swsph_plan();
+    if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
+    pl->cfg = *cfg;
+    pl->tile = cfg->tile ? cfg->tile : 64;
+    pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 512;
+    pl->order = cfg->order;
+    pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
+    *out = pl;
+    return SWSPH_OK;
+}
+
+int swsph_plan_destroy(swsph_plan* pl) {
+    delete pl;
+    return SWSPH_OK;
+}
+
+int swsph_plan_get_tuning(const swsph_plan* pl, int32_t* tile, int32_t* lds_cap, int32_t* order,
+                          int32_t* leaf_max) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    if (tile) *tile = pl->tile;
+    if (lds_cap) *lds_cap = pl->lds_cap;
+    if (order) *order = pl->order;
+    if (leaf_max) *leaf_max = pl->leaf_max;
+    return SWSPH_OK;
+}
+
+int swsph_workspace_bytes(const swsph_plan* pl, int64_t n, int32_t n_box, const int64_t* box_count,
+                          const double* box_size, uint64_t* bytes) {
+    if (!pl || !bytes) return fail(SWSPH_E_ARG, "plan and bytes are required");
+    Geometry G;
+    int r = build_geometry(G, n, n_box, box_count, box_size, pl->tile,
+                           pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
+    if (r) return r;
+    *bytes = G.lay.total;
+    return SWSPH_OK;
+}
+
+int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, false);
+    if (r) return r;
+    if (!ws) return fail(SWSPH_E_ARG, "workspace is NULL");
+    if (((uintptr_t)ws) % ALIGN) return fail(SWSPH_E_ARG, "workspace must be 256-byte aligned");
+    Geometry G;
+    const int64_t one = p->n;
+    r = build_geometry(G, p->n, p->n_box, p->box_count ? p->box_count : &one, p->box_size,
+                       pl->tile, pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
+    if (r) return r;
+    pl->G = G;
+    pl->ws = ws;
+    pl->binned = true;
+    ++pl->bin_id;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    launch_fill_u32(b.cnt, sizeof(Counters) / 4, 0u, s);
+    r = hip_check(hipMemcpyAsync(b.boxtab, pl->G.boxes.data(), sizeof(BoxInfo) * G.n_box,
+                                 hipMemcpyHostToDevice, s),
+                  "copy box table");
+    if (r) return r;
+    launch_fill_u32(b.fine_count, G.n_fine + 1, 0u, s);
+    const bool f64 = pl->cfg.dtype == SWSPH_F64;
+    if (f64) launch_keys<double>(p, b.boxtab, b.keys, b.slot, b.fine_count, b.cnt, s);
+    else launch_keys<float>(p, b.boxtab, b.keys, b.slot, b.fine_count, b.cnt, s);
+    launch_exclusive_scan(b.fine_count, G.n_fine, b.scan_part, b.cstart, s);
+    launch_scatter_stable(G.n, b.keys, b.slot, b.cstart, b.tmpidx, b.perm, b.rank, b.cnt, s);
+    if (f64) {
+        launch_gather<double>(p, b.boxtab, b.keys, b.cstart, b.perm, pl->cfg.eta, b.pos4, b.vel4,
+                              b.hs, s);
+        launch_tiles<double>(G.n_tiles, G.tile, G.n_box, b.boxtab, b.pos4, b.hs, b.tiles, b.order, s);
+    } else {
+        launch_gather<float>(p, b.boxtab, b.keys, b.cstart, b.perm, pl->cfg.eta, b.pos4, b.vel4,
+                             b.hs, s);
+        launch_tiles<float>(G.n_tiles, G.tile, G.n_box, b.boxtab, b.pos4, b.hs, b.tiles, b.order, s);
+    }
+    return hip_check(hipGetLastError(), "swsph_bin launch");
+}
+
+int swsph_density(swsph_plan* pl, const swsph_particles* p, swsph_density_out* o, void* ws,
+                  void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, false);
+    if (r) return r;
+    if (!o || (p->n > 0 && (!o->h || !o->rho || !o->f)))
+        return fail(SWSPH_E_ARG, "density output needs h, rho and f");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int mode = mode_of(pl);
+    if (pl->cfg.dtype == SWSPH_F64) {
+        r = launch_density<double>(b, sc, mode, pl->lds_cap, s);
+        unsort_density<double>(b, o, s);
+    } else {
+        r = launch_density<float>(b, sc, mode, pl->lds_cap, s);
+        unsort_density<float>(b, o, s);
+    }
+    if (r) return fail(SWSPH_E_HIP, "density kernel launch failed");
+    return hip_check(hipGetLastError(), "density");
+}
+
+int swsph_gradient(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                   swsph_gradient_out* o, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
+        return fail(SWSPH_E_ARG, "gradient needs density h, rho and f");
+    if (!o) return fail(SWSPH_E_ARG, "gradient output is NULL");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int mode = mode_of(pl);
+    const int64_t n = b.n;
+    if (pl->cfg.dtype == SWSPH_F64) {
+        launch_prep_dens<double>(b, sc, d, s);
+        r = launch_gradient<double>(b, sc, mode, pl->lds_cap, s);
+        launch_unsort<double>(n, b.rank, (double*)b.g_out, o->v_sig, s);
+        launch_unsort<double>(n, b.rank, (double*)b.g_out + n, o->lap_u, s);
+    } else {
+        launch_prep_dens<float>(b, sc, d, s);
+        r = launch_gradient<float>(b, sc, mode, pl->lds_cap, s);
+        launch_unsort<float>(n, b.rank, (float*)b.g_out, o->v_sig, s);
+        launch_unsort<float>(n, b.rank, (float*)b.g_out + n, o->lap_u, s);
+    }
+    if (r) return fail(SWSPH_E_HIP, "gradient kernel launch failed");
+    return hip_check(hipGetLastError(), "gradient");
+}
+
+int swsph_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                swsph_force_out* o, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
+        return fail(SWSPH_E_ARG, "force needs density h, rho and f");
+    if (!o) return fail(SWSPH_E_ARG, "force output is NULL");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int mode = mode_of(pl);
+    const int64_t n = b.n;
+    if (pl->cfg.dtype == SWSPH_F64) {
+        launch_prep_dens<double>(b, sc, d, s);
+        launch_hmax_pyramid<double>(b, sc, s);
+        r = launch_force<double>(b, sc, mode, pl->lds_cap, s);
+        void* dst[4] = {o->ax, o->ay, o->az, o->dudt};
+        for (int k = 0; k < 4; ++k) launch_unsort<double>(n, b.rank, (double*)b.f_out + k * n, dst[k], s);
+    } else {
+        launch_prep_dens<float>(b, sc, d, s);
+        launch_hmax_pyramid<float>(b, sc, s);
+        r = launch_force<float>(b, sc, mode, pl->lds_cap, s);
+        void* dst[4] = {o->ax, o->ay, o->az, o->dudt};
+        for (int k = 0; k < 4; ++k) launch_unsort<float>(n, b.rank, (float*)b.f_out + k * n, dst[k], s);
+    }
+    if (o->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, o->nint, s);
+    if (r) return fail(SWSPH_E_HIP, "force kernel launch failed");
+    return hip_check(hipGetLastError(), "force");
+}
+
+int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* stream) {
+    if (!pl || !ws || !out) return fail(SWSPH_E_ARG, "plan, ws and out are required");
+    if (!pl->binned || ws != pl->ws) return fail(SWSPH_E_STATE, "no bin on this workspace");
+    Counters c;
+    hipStream_t s = (hipStream_t)stream;
+    int r = hip_check(hipMemcpyAsync(&c, (const char*)ws + pl->G.lay.counters, sizeof c,
+                                     hipMemcpyDeviceToHost, s),
+                      "read stats");
+    if (r) return r;
+    r = hip_check(hipStreamSynchronize(s), "synchronise");
+    if (r) return r;
+    std::memset(out, 0, sizeof *out);
+    out->status = (uint32_t)c.status;
+    out->n_tiles = (uint32_t)pl->G.n_tiles;
+    for (int k = 0; k < 4; ++k) {
+        out->pairs_tested[k] = c.pairs_tested[k];
+        out->pairs_inside[k] = c.pairs_inside[k];
+    }
+    out->newton_sweeps = c.newton_sweeps;
+    out->newton_max = (uint32_t)c.newton_max;
+    out->newton_failed = (uint32_t)c.newton_failed;
+    out->leaves = c.leaves;
+    out->restages = c.restages;
+    if (c.status & SWSPH_ST_DOMAIN) return fail(SWSPH_E_DOMAIN, "a particle lies outside its box");
+    if (c.status & SWSPH_ST_REACH) return fail(SWSPH_E_REACH, "a support radius reaches half a box");
+    if (c.status & SWSPH_ST_CAPACITY) return fail(SWSPH_E_CAPACITY, "internal capacity exceeded");
+    if (c.status & SWSPH_ST_LOOPCAP) return fail(SWSPH_E_CAPACITY, "a device loop hit its cap");
+    if (c.status & SWSPH_ST_NEWTON) return fail(SWSPH_E_NEWTON, "Newton iteration did not converge");
+    return SWSPH_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
+    int r = swsph_bin(pl, p, ws, stream);
+    if (r) return r;
+    r = swsph_density(pl, p, d, ws, stream);
+    if (r) return r;
+    if (go) {
+        r = swsph_gradient(pl, p, d, go, ws, stream);
+        if (r) return r;
+    }
+    if (fo) {
+        r = swsph_force(pl, p, d, fo, ws, stream);
+        if (r) return r;
+    }
+    return SWSPH_OK;
+}
+
+int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                         const swsph_force_grad* g, swsph_input_grad* gi, void* ws, void* stream) {
+    (void)pl; (void)p; (void)d; (void)g; (void)gi; (void)ws; (void)stream;
+    return fail(SWSPH_E_ARG, "swsph_force_backward: not available in this build");
+}
+
+int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream,
+                   const char* cache_path) {
+    (void)pl; (void)p; (void)ws; (void)stream; (void)cache_path;
+    return fail(SWSPH_E_ARG, "swsph_autotune: not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,388 @@
+// bin.hip -- device binning of particles into a hierarchy of cubic cells.
+//
+// The paper's solver splits each periodic box into cubic cells and works on
+// self (one cell) and pair (two neighbouring cells) tasks, recursing in a
+// cell tree down to cells of width ~H (Sec. 2.2, Sec. 2.2.2).  Here the cell
+// hierarchy is implicit: particles are sorted by a Morton key of their cell
+// on the finest grid (2^k cells per dimension in box b), so every coarser
+// cubic cell is one contiguous range of the sorted array and its population
+// is two lookups in the scanned fine histogram.
+//
+// Sort = counting sort on the key: histogram with atomics (which also hands
+// each particle a slot inside its cell), exclusive scan, scatter, and a
+// deterministic fix-up that orders the particles of each fine cell by their
+// input index (so the result is independent of atomic timing).
+#include "launch.h"
+
+namespace swsph {
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n, v);
+}
+
+// ------------------------------------------------------------------ keys
+
+template <typename T>
+__global__ void k_keys(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                       const T* __restrict__ z, const int32_t* __restrict__ box_id,
+                       int32_t n_box, const BoxInfo* __restrict__ boxtab,
+                       uint32_t* __restrict__ keys, int32_t* __restrict__ slot,
+                       int32_t* __restrict__ fine_count, Counters* __restrict__ cnt) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int b = box_id ? box_id[p] : 0;
+    if (b < 0 || b >= n_box) {
+        latch(cnt, SWSPH_ST_DOMAIN);
+        b = b < 0 ? 0 : n_box - 1;
+    }
+    const BoxInfo bi = boxtab[b];
+    const T L = (T)bi.L;
+    T c[3] = {x[p], y[p], z[p]};
+    const int q = 1 << bi.k;
+    const T inv_w = (T)q / L;
+    uint32_t ci[3];
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T v = c[d];
+        if (!(v >= (T)0 && v < L)) bad = true;
+        T f = v * inv_w;
+        int k = (int)f;  // v >= 0: truncation is floor
+        if (!(f >= (T)0)) k = 0;
+        if (k >= q) k = q - 1;
+        ci[d] = (uint32_t)k;
+    }
+    if (bad) latch(cnt, SWSPH_ST_DOMAIN);
+    uint32_t key = (uint32_t)bi.fine_off + morton3(ci[0], ci[1], ci[2]);
+    keys[p] = key;
+    slot[p] = atomicAdd(&fine_count[key], 1);
+}
+
+template <typename T>
+void launch_keys(const swsph_particles* p, const BoxInfo* boxtab, uint32_t* keys,
+                 int32_t* slot, int32_t* fine_count, Counters* cnt, hipStream_t s) {
+    int64_t n = p->n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_keys<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       (const T*)p->x, (const T*)p->y, (const T*)p->z, p->box_id, p->n_box,
+                       boxtab, keys, slot, fine_count, cnt);
+}
+template void launch_keys<float>(const swsph_particles*, const BoxInfo*, uint32_t*, int32_t*,
+                                 int32_t*, Counters*, hipStream_t);
+template void launch_keys<double>(const swsph_particles*, const BoxInfo*, uint32_t*, int32_t*,
+                                  int32_t*, Counters*, hipStream_t);
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of int32 counts, n up to 2^31: blocks of 1024 threads x 4
+// items; block totals scanned by one block (looping over chunks).
+
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_I = 4;
+constexpr int SCAN_B = SCAN_T * SCAN_I;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
+    // wave-level inclusive scan with shuffles, then across the 16 waves
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int w = lane < (int)(blockDim.x >> 6) ? sh[lane] : 0;
+        int y = w;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(y, o, 64);
+            if (lane >= o) y += t;
+        }
+        if (lane < (int)(blockDim.x >> 6)) sh[lane] = y - w;
+        if (lane == (int)(blockDim.x >> 6) - 1) sh[32] = y;
+    }
+    __syncthreads();
+    int excl = sh[wid] + x - v;
+    total = sh[32];
+    __syncthreads();
+    return excl;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                        int32_t* __restrict__ part) {
+    __shared__ int sh[40];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x * SCAN_I;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) s += (base + k < n) ? in[base + k] : 0;
+    int total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_partials(int32_t* __restrict__ part, int64_t nb) {
+    __shared__ int sh[40];
+    int carry = 0;
+    for (int64_t c = 0; c < nb; c += SCAN_T) {
+        int64_t i = c + threadIdx.x;
+        int v = i < nb ? part[i] : 0;
+        int total;
+        int e = block_exclusive_scan(v, sh, total);
+        if (i < nb) part[i] = e + carry;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_final(const int32_t* __restrict__ in, int64_t n,
+                                                       const int32_t* __restrict__ part,
+                                                       int32_t* __restrict__ out) {
+    __shared__ int sh[40];
+    int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x * SCAN_I;
+    int v[SCAN_I];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int e = block_exclusive_scan(s, sh, total) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_I; ++k) {
+        if (base + k < n) out[base + k] = e;
+        e += v[k];
+    }
+    // out[n] = grand total
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[n] = e;
+}
+
+int64_t scan_partials_needed(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
+
+void launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out,
+                           hipStream_t s) {
+    int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_T), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, part, out);
+}
+
+// ------------------------------------------------------- scatter + fix-up
+
+__global__ void k_scatter(int64_t n, const uint32_t* __restrict__ keys,
+                          const int32_t* __restrict__ slot, const int32_t* __restrict__ cstart,
+                          int32_t* __restrict__ tmpidx) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    tmpidx[cstart[keys[p]] + slot[p]] = (int32_t)p;
+}
+
+// Inside each fine cell, order particles by input index: the final position
+// of particle p is the cell start plus the number of the cell's particles
+// with a smaller index.
+constexpr int32_t STABLE_MAX = 1 << 16;  // fine-cell population handled in order
+
+__global__ void k_stable(int64_t n, const uint32_t* __restrict__ keys,
+                         const int32_t* __restrict__ cstart, const int32_t* __restrict__ tmpidx,
+                         int32_t* __restrict__ perm, int32_t* __restrict__ rank,
+                         Counters* __restrict__ cnt) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t p = tmpidx[s];
+    uint32_t key = keys[p];
+    int32_t beg = cstart[key], end = cstart[key + 1];
+    int32_t r = (int32_t)(s - beg);  // slot order if the cell is too crowded
+    if (end - beg <= STABLE_MAX) {
+        r = 0;
+        for (int32_t t = beg; t < end; ++t) r += tmpidx[t] < p;
+    } else if (s == beg) {
+        latch(cnt, SWSPH_ST_LOOPCAP);
+    }
+    perm[beg + r] = p;
+    rank[p] = beg + r;
+}
+
+void launch_scatter_stable(int64_t n, const uint32_t* keys, const int32_t* slot,
+                           const int32_t* cstart, int32_t* tmpidx, int32_t* perm,
+                           int32_t* rank, Counters* cnt, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, n, keys, slot, cstart, tmpidx);
+    hipLaunchKernelGGL(k_stable, dim3(g), dim3(256), 0, s, n, keys, cstart, tmpidx, perm, rank, cnt);
+}
+
+// ---------------------------------------------------------------- gather
+
+// Sorted copies: pos4 = (x, y, z, m), vel4 = (vx, vy, vz, u), hs = h guess.
+// Without a guess, h0 = eta * w_l / cbrt(N_l) from the first enclosing cell
+// (walking up from the fine cell) that holds at least 16 particles.
+template <typename T>
+__global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                         const T* __restrict__ z, const T* __restrict__ vx,
+                         const T* __restrict__ vy, const T* __restrict__ vz,
+                         const T* __restrict__ u, const T* __restrict__ m,
+                         const T* __restrict__ hin, const int32_t* __restrict__ box_id,
+                         const BoxInfo* __restrict__ boxtab, const uint32_t* __restrict__ keys,
+                         const int32_t* __restrict__ cstart, const int32_t* __restrict__ perm,
+                         double eta, V4<T>* __restrict__ pos4, V4<T>* __restrict__ vel4,
+                         T* __restrict__ hs) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t p = perm[s];
+    V4<T> a, b;
+    a.x = x[p]; a.y = y[p]; a.z = z[p]; a.w = m[p];
+    b.x = vx[p]; b.y = vy[p]; b.z = vz[p]; b.w = u ? u[p] : (T)0;
+    pos4[s] = a;
+    vel4[s] = b;
+    T h;
+    if (hin) {
+        h = hin[p];
+    } else {
+        const BoxInfo bi = boxtab[box_id ? box_id[p] : 0];
+        uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
+        const int k = bi.k < 10 ? bi.k : 10;
+        int lev = k;
+        int64_t cntl = 0;
+        for (; lev >= 0; --lev) {
+            int sh = 3 * (k - lev);
+            int64_t beg = bi.fine_off + (int64_t)((mort >> sh) << sh);
+            int64_t end = beg + (int64_t(1) << sh);
+            cntl = cstart[end] - cstart[beg];
+            if (cntl >= 16) break;
+        }
+        if (lev < 0) lev = 0;
+        double w = bi.L / (double)(1 << lev);
+        h = (T)(eta * w / cbrt((double)(cntl > 0 ? cntl : 1)));
+    }
+    hs[s] = h;
+}
+
+template <typename T>
+void launch_gather(const swsph_particles* p, const BoxInfo* boxtab, const uint32_t* keys,
+                   const int32_t* cstart, const int32_t* perm, double eta, void* pos4,
+                   void* vel4, void* hs, hipStream_t s) {
+    int64_t n = p->n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       (const T*)p->x, (const T*)p->y, (const T*)p->z, (const T*)p->vx,
+                       (const T*)p->vy, (const T*)p->vz, (const T*)p->u, (const T*)p->m,
+                       (const T*)p->h, p->box_id, boxtab, keys, cstart, perm, eta,
+                       (V4<T>*)pos4, (V4<T>*)vel4, (T*)hs);
+}
+template void launch_gather<float>(const swsph_particles*, const BoxInfo*, const uint32_t*,
+                                   const int32_t*, const int32_t*, double, void*, void*, void*,
+                                   hipStream_t);
+template void launch_gather<double>(const swsph_particles*, const BoxInfo*, const uint32_t*,
+                                    const int32_t*, const int32_t*, double, void*, void*, void*,
+                                    hipStream_t);
+
+// ----------------------------------------------------------------- tiles
+
+// One wavefront per tile: its particle range, bounding box and largest h.
+template <typename T>
+__global__ void k_tiles(int32_t n_tiles, int32_t tile, int32_t n_box,
+                        const BoxInfo* __restrict__ boxtab, const V4<T>* __restrict__ pos4,
+                        const T* __restrict__ hs, Tile* __restrict__ tiles,
+                        int32_t* __restrict__ order) {
+    int t = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    if (t >= n_tiles) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    // box of tile t: last box with tile_off <= t
+    int lo = 0, hi = n_box - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boxtab[mid].tile_off <= t) lo = mid; else hi = mid - 1;
+    }
+    const BoxInfo bi = boxtab[lo];
+    int j = t - bi.tile_off;
+    int64_t begin = bi.start + (int64_t)j * tile;
+    int64_t cnt = bi.count - (int64_t)j * tile;
+    if (cnt > tile) cnt = tile;
+    if (cnt < 0) cnt = 0;
+    bool act = lane < cnt;
+    float px = 0, py = 0, pz = 0, h = 0;
+    if (act) {
+        V4<T> a = pos4[begin + lane];
+        px = (float)a.x; py = (float)a.y; pz = (float)a.z;
+        h = (float)hs[begin + lane];
+    }
+    float lx = wave_min(act ? px : 3.0e38f), ly = wave_min(act ? py : 3.0e38f),
+          lz = wave_min(act ? pz : 3.0e38f);
+    float ux = wave_max(act ? px : -3.0e38f), uy = wave_max(act ? py : -3.0e38f),
+          uz = wave_max(act ? pz : -3.0e38f);
+    float hm = wave_max(act ? h : 0.0f);
+    if (lane == 0) {
+        Tile tl;
+        tl.begin = (int32_t)begin;
+        tl.count = (int32_t)cnt;
+        tl.box = lo;
+        tl.flags = 0;
+        tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;
+        tl.hi[0] = ux; tl.hi[1] = uy; tl.hi[2] = uz;
+        tl.hmax = hm;
+        tl.cost = (float)cnt;
+        tiles[t] = tl;
+        order[t] = t;
+    }
+}
+
+template <typename T>
+void launch_tiles(int32_t n_tiles, int32_t tile, int32_t n_box, const BoxInfo* boxtab,
+                  const void* pos4, const void* hs, Tile* tiles, int32_t* order, hipStream_t s) {
+    if (n_tiles <= 0) return;
+    const int wpb = 4;
+    hipLaunchKernelGGL(k_tiles<T>, dim3((unsigned)((n_tiles + wpb - 1) / wpb)), dim3(wpb * WAVE),
+                       0, s, n_tiles, tile, n_box, boxtab, (const V4<T>*)pos4, (const T*)hs, tiles,
+                       order);
+}
+template void launch_tiles<float>(int32_t, int32_t, int32_t, const BoxInfo*, const void*,
+                                  const void*, Tile*, int32_t*, hipStream_t);
+template void launch_tiles<double>(int32_t, int32_t, int32_t, const BoxInfo*, const void*,
+                                   const void*, Tile*, int32_t*, hipStream_t);
+
+// ------------------------------------------------------ unsort of outputs
+
+// out[p] = in[rank[p]] for the original particle p.
+template <typename T>
+__global__ void k_unsort(int64_t n, const int32_t* __restrict__ rank, const T* __restrict__ in,
+                         T* __restrict__ out) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < n) out[p] = in[rank[p]];
+}
+template <typename T>
+void launch_unsort(int64_t n, const int32_t* rank, const void* in, void* out, hipStream_t s) {
+    if (n <= 0 || !out) return;
+    hipLaunchKernelGGL(k_unsort<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rank,
+                       (const T*)in, (T*)out);
+}
+template void launch_unsort<float>(int64_t, const int32_t*, const void*, void*, hipStream_t);
+template void launch_unsort<double>(int64_t, const int32_t*, const void*, void*, hipStream_t);
+template void launch_unsort<int32_t>(int64_t, const int32_t*, const void*, void*, hipStream_t);
+
+// in-order -> sorted: out[s] = in[perm[s]]
+template <typename T>
+__global__ void k_sortcopy(int64_t n, const int32_t* __restrict__ perm, const T* __restrict__ in,
+                           T* __restrict__ out) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s < n) out[s] = in[perm[s]];
+}
+template <typename T>
+void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sortcopy<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, perm,
+                       (const T*)in, (T*)out);
+}
+template void launch_sortcopy<float>(int64_t, const int32_t*, const void*, void*, hipStream_t);
+template void launch_sortcopy<double>(int64_t, const int32_t*, const void*, void*, hipStream_t);
+
+}  // namespace swsph

@@ -1,0 +1,90 @@
+// launch.h -- host-side launch wrappers shared by the library's translation
+// units (not part of the C ABI).
+#pragma once
+
+#include "swsph_internal.h"
+
+namespace swsph {
+
+// Scheme constants and options passed to the loop kernels.
+struct Scheme {
+    double eta, eps, gamma, alpha, beta, h_tol;
+    int32_t h_max_iter;
+    uint32_t flags;
+    int32_t leaf_max;
+};
+
+// Device pointers of one bin (all inside the workspace).
+struct BinPtrs {
+    Counters* cnt;
+    BoxInfo* boxtab;
+    uint32_t* phase;
+    uint32_t* keys;
+    int32_t *slot, *tmpidx, *perm, *rank;
+    int32_t *fine_count, *cstart, *scan_part;
+    void *pos4, *vel4, *hs, *dens4;
+    float* hmaxpyr;
+    Tile* tiles;
+    int32_t* order;
+    int32_t *leaf_cnt, *leaf_off, *leaf_part;
+    int2* leaves;
+    int64_t leaf_cap;
+    float* trad;
+    int32_t* tflag;
+    void *d_out, *g_out, *f_out, *adj;
+    int32_t *d_int, *f_int;
+    int64_t n;
+    int32_t n_box, n_tiles, tile;
+    int64_t n_fine, n_pyr;
+};
+
+// Launch modes of the loop kernels.
+enum Mode { MODE_QUEUE = 0, MODE_FLAT = 1, MODE_PER_TASK = 2 };
+
+void launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
+template <typename T>
+void launch_keys(const swsph_particles* p, const BoxInfo* boxtab, uint32_t* keys,
+                 int32_t* slot, int32_t* fine_count, Counters* cnt, hipStream_t s);
+int64_t scan_partials_needed(int64_t n);
+void launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out,
+                           hipStream_t s);
+void launch_scatter_stable(int64_t n, const uint32_t* keys, const int32_t* slot,
+                           const int32_t* cstart, int32_t* tmpidx, int32_t* perm,
+                           int32_t* rank, Counters* cnt, hipStream_t s);
+template <typename T>
+void launch_gather(const swsph_particles* p, const BoxInfo* boxtab, const uint32_t* keys,
+                   const int32_t* cstart, const int32_t* perm, double eta, void* pos4,
+                   void* vel4, void* hs, hipStream_t s);
+template <typename T>
+void launch_tiles(int32_t n_tiles, int32_t tile, int32_t n_box, const BoxInfo* boxtab,
+                  const void* pos4, const void* hs, Tile* tiles, int32_t* order, hipStream_t s);
+template <typename T>
+void launch_unsort(int64_t n, const int32_t* rank, const void* in, void* out, hipStream_t s);
+template <typename T>
+void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, hipStream_t s);
+
+// tasks.hip: mode 0 density, 1 gradient, 2 force; fixup: only flagged tiles
+template <typename T>
+void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s);
+
+// loops.hip
+template <typename T>
+int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
+template <typename T>
+void launch_prep_dens(const BinPtrs& b, const Scheme& sc, const swsph_density_out* d,
+                      hipStream_t s);
+template <typename T>
+void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s);
+template <typename T>
+int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
+template <typename T>
+int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
+template <typename T>
+int launch_step_fused(const BinPtrs& b, const Scheme& sc, int lds_cap, bool do_grad,
+                      bool do_force, hipStream_t s);
+template <typename T>
+int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* g,
+                    const swsph_density_out* d, int lds_cap, hipStream_t s);
+int device_cu_count();
+
+}  // namespace swsph

@@ -1,0 +1,777 @@
+// loops.hip -- gfx950 kernels of the density, gradient and force loops.
+//
+// Work decomposition (MI355X-first; the paper's CUDA kernels are not shown
+// and were written for V100/H100/L40, so nothing is carried over):
+//   * task = one i-tile of up to `tile` consecutive binned particles (one
+//     particle per lane of a 64-wide wavefront);
+//   * the tile's task list (its own and neighbouring cells, i.e. the paper's
+//     self and pair tasks, Sec. 2.2.2) comes from tasks.hip as a CSR of
+//     particle ranges with periodic-image codes;
+//   * the j-particles of those ranges are streamed through the lanes
+//     (coalesced loads), culled against the tile's bounding box by squared
+//     distance, and the survivors are staged in LDS (arrays of 4-vectors);
+//   * every lane then runs over the staged j-particles (LDS broadcast reads)
+//     and accumulates its own sums -- a gather, so no atomics and a fixed
+//     summation order (results are bitwise reproducible);
+//   * the density loop iterates Newton on h over the staged set; a lane whose
+//     h outgrows the staged radius leaves its tile flagged for a fix-up pass
+//     with a wider task list.
+// Launch modes: a persistent kernel whose wavefronts pull tasks from a device
+// queue, a flat launch (one wavefront per task) and one launch per task (the
+// per-task offload baseline).  Every loop has a fixed upper bound.
+#include "launch.h"
+#include "search.h"
+
+namespace swsph {
+
+constexpr int WPB = 4;  // wavefronts per workgroup
+
+template <typename T, int CAP, int NV>
+struct WaveMem {
+    V4<T> s[NV][CAP];          // staged j-particles
+    int32_t lbeg[WAVE];        // current batch of task-list leaves
+    int32_t lpre[WAVE + 1];
+    int32_t lshift[WAVE];
+};
+
+template <typename T>
+struct KArgs {
+    const BoxInfo* boxtab;
+    const Tile* tiles;
+    const int32_t* order;
+    int32_t n_tiles;
+    int32_t task;              // per-task launch: the task to run
+    const int32_t* leaf_cnt;
+    const int32_t* leaf_off;
+    const int2* leaves;
+    int64_t leaf_cap;
+    float* trad;
+    int32_t* tflag;
+    const V4<T>* pos4;
+    const V4<T>* vel4;
+    T* hs;
+    const V4<T>* dens4;
+    T* out;                    // sorted outputs, arrays of n
+    int32_t* iout;             // sorted int outputs, arrays of n
+    int64_t n;
+    Counters* cnt;
+    unsigned long long* queue;
+    T eta, eps, gamma, alpha, beta, h_tol;
+    int32_t h_max_iter;
+    uint32_t flags;
+    int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
+};
+
+enum { L_DENS = 0, L_GRAD = 1, L_FORCE = 2 };
+
+template <int LK> struct LoopNV;
+template <> struct LoopNV<L_DENS> { static constexpr int NV = 2; };
+template <> struct LoopNV<L_GRAD> { static constexpr int NV = 3; };
+template <> struct LoopNV<L_FORCE> { static constexpr int NV = 4; };
+
+template <typename T> __device__ __forceinline__ T int_as(int32_t v);
+template <> __device__ __forceinline__ float int_as<float>(int32_t v) { return __int_as_float(v); }
+template <> __device__ __forceinline__ double int_as<double>(int32_t v) { return (double)v; }
+template <typename T> __device__ __forceinline__ int32_t as_int(T v);
+template <> __device__ __forceinline__ int32_t as_int<float>(float v) { return __float_as_int(v); }
+template <> __device__ __forceinline__ int32_t as_int<double>(double v) { return (int32_t)v; }
+
+// Stream the j-particles of tile t's task list through the lanes, cull them
+// against the tile box (radius R, or the j-particle's own support for the
+// force loop), stage survivors in LDS; flush(nsurv) is called whenever the
+// buffer could overflow (the buffer is empty afterwards).  Returns the
+// number of staged survivors left for the caller.
+template <int LK, typename T, int CAP, class WM, class Flush>
+__device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
+                          T R2, int& flushes, Flush&& flush) {
+    const int lane = lane_id();
+    const int64_t off = a.leaf_off[t];
+    int64_t nl = a.leaf_cnt[t];
+    if (off + nl > a.leaf_cap) nl = a.leaf_cap > off ? a.leaf_cap - off : 0;
+    const T L = (T)bi.L;
+    int nsurv = 0;
+    flushes = 0;
+    for (int64_t lb = 0; lb < nl; lb += WAVE) {
+        const int nb = (int)min((int64_t)WAVE, nl - lb);
+        int32_t beg = 0, num = 0;
+        int sh = 13;
+        if (lane < nb) unpack_leaf(a.leaves[off + lb + lane], beg, num, sh);
+        int total;
+        const int e = wave_excl_scan(num, total);
+        m.lbeg[lane] = beg;
+        m.lpre[lane] = e;
+        m.lshift[lane] = sh;
+        if (lane == 0) m.lpre[WAVE] = total;
+        wave_sync();
+        for (int base = 0; base < total; base += WAVE) {
+            if (nsurv + WAVE > CAP) {
+                flush(nsurv);
+                nsurv = 0;
+                ++flushes;
+            }
+            const int v = base + lane;
+            bool pass = false;
+            V4<T> pa;
+            T xs = 0, ys = 0, zs = 0;
+            int j = 0;
+            if (v < total) {
+                int lo = 0, hi = nb - 1;
+                while (lo < hi) {  // last leaf whose prefix is <= v
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                j = m.lbeg[lo] + (v - m.lpre[lo]);
+                if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid task list
+                int sx, sy, sz;
+                shift_of(m.lshift[lo], sx, sy, sz);
+                pa = a.pos4[j];
+                xs = pa.x + (T)sx * L;
+                ys = pa.y + (T)sy * L;
+                zs = pa.z + (T)sz * L;
+                const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+                const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+                const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+                const T d2 = dist2_unfused(gx, gy, gz);
+                T crit = R2;
+                if (LK == L_FORCE) {
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    crit = max(crit, mul_unfused(Hj, Hj));
+                }
+                pass = d2 < crit;
+            }
+            const unsigned long long pm = ballot(pass);
+            if (pass) {
+                const int k = nsurv + mbcnt(pm);
+                const V4<T> va = a.vel4[j];
+                if (LK == L_DENS) {
+                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
+                } else if (LK == L_GRAD) {
+                    const V4<T> da = a.dens4[j];  // (rho, f, c, A)
+                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                    m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
+                } else {
+                    const V4<T> da = a.dens4[j];
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                    m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
+                    m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
+                }
+            }
+            nsurv += __popcll(pm);
+            wave_sync();
+        }
+    }
+    return nsurv;
+}
+
+// ---------------------------------------------------------------- kernels
+// M4 pieces on q = r/H:  w, s1 = 3w + q w', g = w'/q  (all finite at q = 0).
+
+template <typename T>
+__device__ __forceinline__ void m4_terms(T q, T inv_q, T& w, T& s1, T& g) {
+    const T t = (T)1 - q;
+    const T q2 = q * q;
+    if (q < (T)0.5) {
+        w = (T)1 + q2 * ((T)6 * q - (T)6);
+        s1 = (T)3 + q2 * ((T)36 * q - (T)30);
+        g = (T)18 * q - (T)12;
+    } else {
+        const T t2 = t * t;
+        w = (T)2 * t2 * t;
+        s1 = (T)6 * t2 * ((T)1 - (T)2 * q);
+        g = (T)-6 * t2 * inv_q;
+    }
+}
+// w'(q)
+template <typename T> __device__ __forceinline__ T m4_dw(T q) {
+    const T t = (T)1 - q;
+    return q < (T)0.5 ? q * ((T)18 * q - (T)12) : (T)-6 * t * t;
+}
+
+__device__ __forceinline__ TileGeom geom_of(const Tile& tl) {
+    TileGeom g;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
+    return g;
+}
+
+// ------------------------------------------------------------ density tile
+
+template <typename T, int CAP>
+__device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
+    const Tile tl = a.tiles[t];
+    if (tl.count <= 0) return;
+    if (a.fixup && a.tflag[t] == 0) return;
+    const int lane = lane_id();
+    const bool act = lane < tl.count;
+    const int i = tl.begin + (act ? lane : 0);
+    const BoxInfo bi = a.boxtab[tl.box];
+    const V4<T> pi = a.pos4[i];
+    const V4<T> vi = a.vel4[i];
+    T h = a.hs[i];
+    const bool fixed = (a.flags & SWSPH_FIXED_H) != 0;
+    const TileGeom g = geom_of(tl);
+    const T L = (T)bi.L;
+    const T Rcap = (T)(0.5f * (float)bi.L * (1.0f - 1e-6f));
+    const T eps = a.eps;
+    const T cnorm = (T)(8.0 / PI_D);
+    // root of sum_j w(q_ij) = Tt  <=>  h^3 n(h) = eta^3
+    const T Tt = a.eta * a.eta * a.eta * eps * eps * eps / cnorm;
+    const T tiny = (sizeof(T) == 4) ? (T)2.4e-7 : (T)4.5e-16;
+    const T R = (T)a.trad[t];
+    const T hstage = R / eps;
+    (void)L;
+
+    T lo_h = 0, hi_h = hstage;
+    bool has_upper = false;
+    bool conv = fixed || !act;
+    bool pend = false, failed = false;
+    T want = 0;
+    int iters = a.fixup ? max(0, a.iout[a.n + i] < 0 ? -a.iout[a.n + i] : a.iout[a.n + i]) : 0;
+    const int iters0 = iters;
+    T S0 = 0, S1 = 0, Sr = 0, Sdr = 0, Dv = 0, Cx = 0, Cy = 0, Cz = 0;
+    int cnt = 0;
+    unsigned long long tested = 0;
+    T H = eps * h;
+    T H2 = act ? mul_unfused(H, H) : (T)-1;
+    T invH = (T)1 / H;
+    auto sweep = [&](int ns) {
+        for (int k = 0; k < ns; ++k) {
+            const V4<T> sj = m.s[0][k];
+            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+            const T r2 = dist2_unfused(dx, dy, dz);
+            if (r2 < H2) {
+                const V4<T> vj = m.s[1][k];
+                const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
+                const T q = r2 * inv_r * invH;
+                T w, s1, gq;
+                m4_terms(q, H * inv_r, w, s1, gq);
+                S0 += w;
+                S1 += s1;
+                Sr += sj.w * w;
+                Sdr += sj.w * s1;
+                const T ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+                const T mg = sj.w * gq;
+                Dv += mg * (ux * dx + uy * dy + uz * dz);
+                Cx += mg * (uy * dz - uz * dy);
+                Cy += mg * (uz * dx - ux * dz);
+                Cz += mg * (ux * dy - uy * dx);
+                ++cnt;
+            }
+        }
+        tested += (unsigned long long)ns;
+    };
+    auto zero = [&]() {
+        S0 = S1 = Sr = Sdr = Dv = Cx = Cy = Cz = 0;
+        cnt = 0;
+    };
+    const T R2 = R * R;
+    int flushes = 0;
+    int ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, flushes, sweep);
+    sweep(ns);
+    const bool cached = flushes == 0;
+    for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
+        ++iters;
+        if (!conv && !pend) {
+            const T G = S0;
+            if (fabs(G - Tt) <= a.h_tol * Tt) {
+                conv = true;
+            } else {
+                const T dG = ((T)3 * S0 - S1) / h;
+                if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
+                T hn = h - (G - Tt) / dG;
+                const bool ok = dG > (T)0 && hn > lo_h && hn < hi_h;
+                if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
+                if (!has_upper && hn >= hstage) {
+                    // the root lies beyond the staged radius: fix-up pass
+                    if (R >= Rcap) { failed = true; conv = true; }
+                    else { pend = true; want = hn; }
+                } else if (fabs(hn - h) <= tiny * h) {
+                    conv = true;
+                } else {
+                    h = hn;
+                }
+            }
+        }
+        if (ballot(!conv && !pend) == 0ull) break;
+        if (sweeps == a.h_max_iter) break;
+        H = eps * h;
+        H2 = act ? mul_unfused(H, H) : (T)-1;
+        invH = (T)1 / H;
+        zero();
+        if (cached) {
+            sweep(ns);
+        } else {
+            int fl = 0;
+            ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, fl, sweep);
+            sweep(ns);
+        }
+    }
+    const bool last = a.fixup == 2;
+    if (pend && last) { failed = true; pend = false; }
+    if (!conv && !pend && act) failed = true;
+    // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
+    if (act) {
+        const T Hh = eps * h;
+        const T iH = (T)1 / Hh;
+        const T k3 = cnorm * iH * iH * iH;
+        const T k5 = k3 * iH * iH;
+        const T rho = k3 * Sr;
+        const T drho = -k3 * Sdr / h;
+        const int64_t n = a.n;
+        T* o = a.out;
+        o[0 * n + i] = h;
+        o[1 * n + i] = rho;
+        o[2 * n + i] = drho;
+        o[3 * n + i] = k3 * S0;
+        o[4 * n + i] = -k3 * S1 / h;
+        o[5 * n + i] = -k5 * Dv / rho;
+        o[6 * n + i] = k5 * Cx / rho;
+        o[7 * n + i] = k5 * Cy / rho;
+        o[8 * n + i] = k5 * Cz / rho;
+        o[9 * n + i] = (T)1 / ((T)1 + h * drho / ((T)3 * rho));
+        a.iout[0 * n + i] = cnt - 1;
+        a.iout[1 * n + i] = failed ? -iters : iters;
+        a.hs[i] = pend ? want : h;
+    }
+    const unsigned long long pmask = ballot(pend);
+    const unsigned long long fmask = ballot(failed);
+    const T wmax = wave_max(pend ? want : (T)0);
+    const unsigned long long ins = (unsigned long long)wave_sum(act ? cnt : 0);
+    if (lane == 0) {
+        if (pmask) {
+            T Rn = eps * wmax * (T)1.125;
+            if (!(Rn < Rcap)) Rn = Rcap;
+            a.trad[t] = (float)Rn;
+            a.tflag[t] = 1;
+            atomicAdd(&a.cnt->restages, 1ull);
+        } else {
+            a.tflag[t] = 0;
+        }
+        atomicAdd(&a.cnt->pairs_tested[0], tested * (unsigned long long)tl.count);
+        atomicAdd(&a.cnt->pairs_inside[0], ins);
+        atomicAdd(&a.cnt->newton_sweeps, (unsigned long long)(iters - iters0));
+        atomicMax(&a.cnt->newton_max, (unsigned long long)iters);
+        if (fmask) {
+            atomicAdd(&a.cnt->newton_failed, (unsigned long long)__popcll(fmask));
+            latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
+        }
+    }
+}
+
+// ----------------------------------------------------------- gradient tile
+
+template <typename T, int CAP>
+__device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
+    const Tile tl = a.tiles[t];
+    if (tl.count <= 0) return;
+    const int lane = lane_id();
+    const bool act = lane < tl.count;
+    const int i = tl.begin + (act ? lane : 0);
+    const BoxInfo bi = a.boxtab[tl.box];
+    const V4<T> pi = a.pos4[i];
+    const V4<T> vi = a.vel4[i];
+    const V4<T> di = a.dens4[i];
+    const T h = a.hs[i];
+    const TileGeom g = geom_of(tl);
+    const T eps = a.eps;
+    const T H = mul_unfused(eps, h);
+    const T H2 = act ? mul_unfused(H, H) : (T)-1;
+    const T invH = (T)1 / H;
+    const T R = (T)a.trad[t];
+    const T ci = di.z, ui = vi.w;
+    T vsig = (T)2 * ci, lap = 0;
+    unsigned long long tested = 0;
+    int inside = 0;
+    auto sweep = [&](int ns) {
+        for (int k = 0; k < ns; ++k) {
+            const V4<T> sj = m.s[0][k];
+            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+            const T r2 = dist2_unfused(dx, dy, dz);
+            if (r2 < H2 && r2 > (T)0) {
+                const V4<T> vj = m.s[1][k];
+                const T uj = m.s[2][k].x;
+                const T inv_r = fast_rsqrt(r2);
+                const T q = r2 * inv_r * invH;
+                const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+                const T mu = vr < (T)0 ? vr * inv_r : (T)0;
+                const T s = ci + vj.w - a.beta * mu;
+                vsig = s > vsig ? s : vsig;
+                const T t1 = (T)1 - q;
+                const T gq = q < (T)0.5 ? (T)18 * q - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
+                lap += sj.w * (ui - uj) * gq;
+                ++inside;
+            }
+        }
+        tested += (unsigned long long)ns;
+    };
+    int flushes = 0;
+    const int ns = stage_tile<L_GRAD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
+    sweep(ns);
+    if (act) {
+        const T k5 = (T)(8.0 / PI_D) * invH * invH * invH * invH * invH;
+        a.out[0 * a.n + i] = vsig;
+        a.out[1 * a.n + i] = (T)2 * k5 * lap;
+    }
+    const unsigned long long ins = (unsigned long long)wave_sum(act ? inside : 0);
+    if (lane == 0) {
+        atomicAdd(&a.cnt->pairs_tested[1], tested * (unsigned long long)tl.count);
+        atomicAdd(&a.cnt->pairs_inside[1], ins);
+    }
+}
+
+// -------------------------------------------------------------- force tile
+
+template <typename T, int CAP>
+__device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
+    const Tile tl = a.tiles[t];
+    if (tl.count <= 0) return;
+    const int lane = lane_id();
+    const bool act = lane < tl.count;
+    const int i = tl.begin + (act ? lane : 0);
+    const BoxInfo bi = a.boxtab[tl.box];
+    const V4<T> pi = a.pos4[i];
+    const V4<T> vi = a.vel4[i];
+    const V4<T> di = a.dens4[i];  // (rho, f, c, A)
+    const T h = a.hs[i];
+    const TileGeom g = geom_of(tl);
+    const T eps = a.eps;
+    const T H = mul_unfused(eps, h);
+    const T H2 = act ? mul_unfused(H, H) : (T)-1;
+    const T invH = (T)1 / H;
+    const T R = (T)a.trad[t];
+    const T cn = (T)(8.0 / PI_D);
+    const T kgi = cn * invH * invH * invH * invH;
+    const T rhoi = di.x, fi = di.y, ci = di.z, Ai = di.w;
+    const bool visc = (a.flags & SWSPH_NO_VISC) == 0;
+    const T alpha = a.alpha, beta = a.beta;
+    T ax = 0, ay = 0, az = 0, du = 0;
+    int nint = 0;
+    unsigned long long tested = 0;
+    auto sweep = [&](int ns) {
+        for (int k = 0; k < ns; ++k) {
+            const V4<T> sj = m.s[0][k];
+            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+            const T r2 = dist2_unfused(dx, dy, dz);
+            const T H2j = sj.w;
+            const int jj = as_int<T>(m.s[3][k].y);
+            if (act && r2 < max(H2, H2j) && jj != i) {
+                ++nint;
+                if (r2 > (T)0) {
+                    const V4<T> vj = m.s[1][k];
+                    const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
+                    const T rhoj = m.s[3][k].x;
+                    const T inv_r = fast_rsqrt(r2);
+                    const T r = r2 * inv_r;
+                    const T gi = r2 < H2 ? kgi * m4_dw(r * invH) : (T)0;
+                    const T ihj = cj.w;
+                    const T gj = r2 < H2j ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
+                    const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+                    const T vdote = vr * inv_r;
+                    T nu = 0;
+                    if (visc) {
+                        const T mu = vdote < (T)0 ? vdote : (T)0;
+                        const T vs = ci + vj.w - beta * mu;
+                        nu = -alpha * mu * vs / (rhoi + rhoj);
+                    }
+                    const T mfg = cj.x * fi * gi + cj.z * gj;
+                    const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
+                    const T sr = sa * inv_r;
+                    ax -= sr * dx;
+                    ay -= sr * dy;
+                    az -= sr * dz;
+                    du += vdote * (cj.x * Ai * gi + (T)0.25 * nu * mfg);
+                }
+            }
+        }
+        tested += (unsigned long long)ns;
+    };
+    int flushes = 0;
+    const int ns = stage_tile<L_FORCE, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
+    sweep(ns);
+    if (act) {
+        a.out[0 * a.n + i] = ax;
+        a.out[1 * a.n + i] = ay;
+        a.out[2 * a.n + i] = az;
+        a.out[3 * a.n + i] = du;
+        a.iout[i] = nint;
+    }
+    const unsigned long long ins = (unsigned long long)wave_sum(act ? nint : 0);
+    if (lane == 0) {
+        atomicAdd(&a.cnt->pairs_tested[2], tested * (unsigned long long)tl.count);
+        atomicAdd(&a.cnt->pairs_inside[2], ins);
+    }
+}
+
+// ----------------------------------------------------------------- drivers
+
+template <int LK, typename T, int CAP>
+__device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t) {
+    if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t);
+    else if (LK == L_GRAD) gradient_tile<T, CAP>(*(WaveMem<T, CAP, 3>*)wm, a, t);
+    else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t);
+}
+
+template <int LK, typename T, int CAP>
+__global__ void __launch_bounds__(WPB * WAVE) k_loop(KArgs<T> a, int mode) {
+    SWSPH_DYN_SHARED char smem[];
+    constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
+    const int wave = threadIdx.x / WAVE;
+    char* wm = smem + wave * WMS;
+    if (mode == MODE_QUEUE) {
+        // every wavefront pops tasks until the queue is drained; the loop
+        // runs at most n_tiles + 1 times per wavefront
+        for (int guard = 0; guard <= a.n_tiles; ++guard) {
+            int t = 0;
+            if (lane_id() == 0) t = (int)atomicAdd(a.queue, 1ull);
+            t = uniform(__shfl(t, 0, WAVE));
+            if (t >= a.n_tiles || t < 0) break;
+            run_tile<LK, T, CAP>(wm, a, a.order[t]);
+        }
+    } else if (mode == MODE_FLAT) {
+        const int t = blockIdx.x * WPB + wave;
+        if (t < a.n_tiles) run_tile<LK, T, CAP>(wm, a, a.order[t]);
+    } else {
+        if (wave == 0 && a.task >= 0 && a.task < a.n_tiles) run_tile<LK, T, CAP>(wm, a, a.task);
+    }
+}
+
+int device_cu_count() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+template <typename T>
+static KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
+    KArgs<T> a;
+    a.boxtab = b.boxtab;
+    a.tiles = b.tiles;
+    a.order = b.order;
+    a.n_tiles = b.n_tiles;
+    a.task = 0;
+    a.leaf_cnt = b.leaf_cnt;
+    a.leaf_off = b.leaf_off;
+    a.leaves = b.leaves;
+    a.leaf_cap = b.leaf_cap;
+    a.trad = b.trad;
+    a.tflag = b.tflag;
+    a.pos4 = (const V4<T>*)b.pos4;
+    a.vel4 = (const V4<T>*)b.vel4;
+    a.hs = (T*)b.hs;
+    a.dens4 = (const V4<T>*)b.dens4;
+    a.out = nullptr;
+    a.iout = nullptr;
+    a.n = b.n;
+    a.cnt = b.cnt;
+    a.queue = nullptr;
+    a.eta = (T)sc.eta;
+    a.eps = (T)sc.eps;
+    a.gamma = (T)sc.gamma;
+    a.alpha = (T)sc.alpha;
+    a.beta = (T)sc.beta;
+    a.h_tol = (T)sc.h_tol;
+    a.h_max_iter = sc.h_max_iter;
+    a.flags = sc.flags;
+    a.fixup = 0;
+    return a;
+}
+
+template <int LK, typename T, int CAP>
+static int launch_loop_cap(KArgs<T> a, int mode, int queue_slot, hipStream_t s) {
+    constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
+    const size_t shm = WMS * WPB;
+    auto kern = k_loop<LK, T, CAP>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm) != hipSuccess)
+            return -1;
+        attr_set = true;
+    }
+    if (a.n_tiles <= 0) return 0;
+    a.queue = &a.cnt->queue[queue_slot];
+    if (mode == MODE_QUEUE) {
+        launch_fill_u32(a.queue, 2, 0u, s);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WPB * WAVE,
+                                                         shm) != hipSuccess)
+            per_cu = 1;
+        if (per_cu < 1) per_cu = 1;
+        int64_t blocks = (int64_t)per_cu * device_cu_count();
+        const int64_t need = (a.n_tiles + WPB - 1) / WPB;
+        if (blocks > need) blocks = need;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, a, (int)MODE_QUEUE);
+    } else if (mode == MODE_FLAT) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)((a.n_tiles + WPB - 1) / WPB)), dim3(WPB * WAVE),
+                           shm, s, a, (int)MODE_FLAT);
+    } else {
+        for (int t = 0; t < a.n_tiles; ++t) {
+            a.task = t;
+            hipLaunchKernelGGL(kern, dim3(1), dim3(WAVE), WMS, s, a, (int)MODE_PER_TASK);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+template <int LK, typename T, int CAP>
+constexpr bool fits() {
+    return WPB * sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>) <= LDS_LIMIT;
+}
+
+// Largest staging capacity <= lds_cap whose workgroup fits in the LDS.
+template <int LK, typename T>
+static int launch_loop(KArgs<T> a, int mode, int lds_cap, int queue_slot, hipStream_t s) {
+    if (lds_cap >= 512 && fits<LK, T, 512>()) return launch_loop_cap<LK, T, 512>(a, mode, queue_slot, s);
+    if (lds_cap >= 256 && fits<LK, T, 256>()) return launch_loop_cap<LK, T, 256>(a, mode, queue_slot, s);
+    static_assert(fits<LK, T, 128>(), "staging buffer does not fit");
+    return launch_loop_cap<LK, T, 128>(a, mode, queue_slot, s);
+}
+
+// Density: the first pass, then up to three fix-up passes for tiles whose
+// Newton iteration needed a wider task list (the last one latches failures).
+template <typename T>
+int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
+    KArgs<T> a = make_args<T>(b, sc);
+    a.out = (T*)b.d_out;
+    a.iout = b.d_int;
+    launch_tasks<T>(b, sc, 0, false, s);
+    int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
+    if (r || (sc.flags & SWSPH_FIXED_H)) return r;
+    for (int pass = 1; pass <= 3 && !r; ++pass) {
+        launch_tasks<T>(b, sc, 0, true, s);
+        a.fixup = pass == 3 ? 2 : 1;
+        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, lds_cap, 0, s);
+    }
+    return r;
+}
+template <typename T>
+int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
+    KArgs<T> a = make_args<T>(b, sc);
+    a.out = (T*)b.g_out;
+    launch_tasks<T>(b, sc, 1, false, s);
+    return launch_loop<L_GRAD, T>(a, mode, lds_cap, 1, s);
+}
+template <typename T>
+int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
+    KArgs<T> a = make_args<T>(b, sc);
+    a.out = (T*)b.f_out;
+    a.iout = b.f_int;
+    launch_tasks<T>(b, sc, 2, false, s);
+    return launch_loop<L_FORCE, T>(a, mode, lds_cap, 2, s);
+}
+
+template int launch_density<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_density<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_gradient<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_gradient<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_force<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_force<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+
+// ------------------------------------------------- per-particle preparation
+
+// Gather the caller's density results (original order) into binned order:
+// hs = h, dens4 = (rho, f, c, A) with c = sqrt(gamma (gamma-1) u) and
+// A = f P / rho^2 = f (gamma-1) u / rho.
+template <typename T>
+__global__ void k_prep_dens(int64_t n, const int32_t* __restrict__ perm, const T* __restrict__ h,
+                            const T* __restrict__ rho, const T* __restrict__ f,
+                            const V4<T>* __restrict__ vel4, T gamma, T* __restrict__ hs,
+                            V4<T>* __restrict__ dens4) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t p = perm[s];
+    const T u = vel4[s].w;
+    const T r = rho[p], ff = f[p];
+    hs[s] = h[p];
+    const T gm1 = gamma - (T)1;
+    dens4[s] = V4<T>{r, ff, sqrt(gamma * gm1 * u), ff * gm1 * u / r};
+}
+
+template <typename T>
+void launch_prep_dens(const BinPtrs& b, const Scheme& sc, const swsph_density_out* d,
+                      hipStream_t s) {
+    if (b.n <= 0) return;
+    hipLaunchKernelGGL(k_prep_dens<T>, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, s, b.n,
+                       b.perm, (const T*)d->h, (const T*)d->rho, (const T*)d->f,
+                       (const V4<T>*)b.vel4, (T)sc.gamma, (T*)b.hs, (V4<T>*)b.dens4);
+}
+template void launch_prep_dens<float>(const BinPtrs&, const Scheme&, const swsph_density_out*,
+                                      hipStream_t);
+template void launch_prep_dens<double>(const BinPtrs&, const Scheme&, const swsph_density_out*,
+                                       hipStream_t);
+
+// Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
+// of every box: fine cells by atomic max over particles, then each fine cell
+// pushes its value up while it raises the parent.
+// Box of the binned particle s: boxes occupy consecutive ranges.
+__device__ __forceinline__ int box_of_sorted(int64_t s, int32_t n_box,
+                                             const BoxInfo* __restrict__ boxtab) {
+    int lo = 0, hi = n_box - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxtab[mid].start <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void k_hmax_fine(int64_t n, const int32_t* __restrict__ perm,
+                            const uint32_t* __restrict__ keys, int32_t n_box,
+                            const BoxInfo* __restrict__ boxtab, const T* __restrict__ hs, T eps,
+                            float* __restrict__ pyr) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t p = perm[s];
+    const BoxInfo bi = boxtab[box_of_sorted(s, n_box, boxtab)];
+    const uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
+    const float H = (float)(eps * hs[s]) * (1.0f + 1e-6f);
+    atomicMax((int*)&pyr[bi.pyr_off + pyr_level_off(bi.k) + mort], __float_as_int(H));
+}
+
+__global__ void k_hmax_up(int64_t n_fine, int32_t n_box, const BoxInfo* __restrict__ boxtab,
+                          float* __restrict__ pyr) {
+    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= n_fine) return;
+    int lo = 0, hi = n_box - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxtab[mid].fine_off <= f) lo = mid; else hi = mid - 1;
+    }
+    const BoxInfo bi = boxtab[lo];
+    const int k = bi.k < 10 ? bi.k : 10;
+    const uint32_t mort = (uint32_t)(f - bi.fine_off);
+    const float v = pyr[bi.pyr_off + pyr_level_off(k) + mort];
+    if (!(v > 0.f)) return;
+    for (int l = k - 1; l >= 0; --l) {
+        float* pp = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
+        if (*pp >= v) break;
+        atomicMax((int*)pp, __float_as_int(v));
+    }
+}
+
+template <typename T>
+void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s) {
+    launch_fill_u32(b.hmaxpyr, b.n_pyr, 0u, s);
+    if (b.n <= 0) return;
+    hipLaunchKernelGGL(k_hmax_fine<T>, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, s, b.n,
+                       b.perm, b.keys, b.n_box, b.boxtab, (const T*)b.hs,
+                       (T)sc.eps, b.hmaxpyr);
+    hipLaunchKernelGGL(k_hmax_up, dim3((unsigned)((b.n_fine + 255) / 256)), dim3(256), 0, s,
+                       b.n_fine, b.n_box, b.boxtab, b.hmaxpyr);
+}
+template void launch_hmax_pyramid<float>(const BinPtrs&, const Scheme&, hipStream_t);
+template void launch_hmax_pyramid<double>(const BinPtrs&, const Scheme&, hipStream_t);
+
+}  // namespace swsph

@@ -1,0 +1,198 @@
+// swsph_internal.h -- shared definitions of the gfx950 SPH library (device
+// helpers, workspace layout, per-box tables).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "swsph.h"
+
+// Dynamic LDS of a kernel.
+#ifndef SWSPH_DYN_SHARED
+#define SWSPH_DYN_SHARED extern __shared__ __align__(16)
+#endif
+
+namespace swsph {
+
+constexpr int WAVE = 64;
+constexpr double PI_D = 3.14159265358979323846;
+
+// ------------------------------------------------------------------ tables
+
+// Per-box geometry, computed on the host from the particle counts and box
+// sizes and copied into the workspace by swsph_bin.
+struct BoxInfo {
+    double L;           // side length
+    int64_t start;      // first particle of the box in binned (sorted) order
+    int64_t count;      // particles in the box
+    int64_t fine_off;   // offset of the box's cells in the fine cell table
+    int64_t pyr_off;    // offset of the box's level-0 entry in the H-max pyramid
+    int32_t k;          // fine level: 2^k cells per dimension
+    int32_t tile_off;   // first tile of the box
+    int32_t n_tiles;    // tiles of the box
+    int32_t pad;
+};
+
+// One i-tile task: up to `tile` consecutive binned particles of one box.
+struct Tile {
+    int32_t begin;      // first binned particle
+    int32_t count;      // particles (<= tile size)
+    int32_t box;
+    int32_t flags;
+    float lo[3], hi[3]; // bounding box of the tile's particles
+    float hmax;         // largest smoothing length in the tile
+    float cost;         // work estimate (candidate pairs)
+};
+
+// Device counters (start of the workspace).  All 64-bit for atomics.
+struct Counters {
+    unsigned long long status;
+    unsigned long long pairs_tested[4];
+    unsigned long long pairs_inside[4];
+    unsigned long long newton_sweeps;
+    unsigned long long newton_max;
+    unsigned long long newton_failed;
+    unsigned long long leaves;
+    unsigned long long restages;
+    unsigned long long queue[8];       // task-queue heads of the loops
+    unsigned long long leaf_need;      // leaves requested by the last task build
+    unsigned long long reserved[9];
+};
+
+enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };
+
+// Byte offsets of every workspace region (computed on the host).
+struct Layout {
+    uint64_t counters, boxtab, phase;      // phase: per-box done counters (2 per box)
+    uint64_t keys, slot, tmpidx, perm, rank;
+    uint64_t fine_count, cstart, scan_part;
+    uint64_t pos4, vel4, hs, dens4, hmaxpyr;
+    uint64_t tiles, order;
+    // task lists (CSR of cells per tile) and density fix-up state
+    uint64_t leaf_cnt, leaf_off, leaf_part, leaves, trad, tflag;
+    // sorted-order results
+    uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
+    uint64_t d_int;     // 2 arrays of int32: nngb iters
+    uint64_t g_out;     // 2 arrays of T
+    uint64_t f_out;     // 4 arrays of T
+    uint64_t f_int;     // 1 array of int32
+    uint64_t adj;       // adjoint scratch: 16 arrays of T
+    uint64_t total;
+};
+
+// ----------------------------------------------------------- device helpers
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using V4 = typename Vec4<T>::type;
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot((int)p); }
+
+// Lanes below this one whose bit is set in mask.
+__device__ __forceinline__ int mbcnt(unsigned long long mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Make LDS stores of every lane visible to every lane of the same wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }
+__device__ __forceinline__ double shfl_xor(double v, int m) { return __shfl_xor(v, m, WAVE); }
+__device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, WAVE); }
+
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) { T o = shfl_xor(v, m); v = o > v ? o : v; }
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) { T o = shfl_xor(v, m); v = o < v ? o : v; }
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
+    return v;
+}
+
+// Squared distance in a fixed, unfused order: ((dx*dx + dy*dy) + dz*dz).
+// Integer neighbour counts depend on it bit for bit, so no product may be
+// contracted into an addition here.
+__device__ __forceinline__ float dist2_unfused(float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+    float a = dx * dx;
+    float b = dy * dy;
+    float c = dz * dz;
+    float s = a + b;
+    return s + c;
+}
+__device__ __forceinline__ double dist2_unfused(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    double s = a + b;
+    return s + c;
+}
+__device__ __forceinline__ float sub_unfused(float a, float b) { return a - b; }
+__device__ __forceinline__ float add_unfused(float a, float b) { return a + b; }
+__device__ __forceinline__ float mul_unfused(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double mul_unfused(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+__device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ void latch(Counters* c, unsigned bits) {
+    atomicOr(&c->status, (unsigned long long)bits);
+}
+
+// Morton code: bit b of cx -> bit 3b, of cy -> 3b+1, of cz -> 3b+2.
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+__host__ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+// Offset of level l inside one box's pyramid (levels 0..k, 8^l cells each).
+__host__ __device__ __forceinline__ int64_t pyr_level_off(int l) {
+    return ((int64_t(1) << (3 * l)) - 1) / 7;
+}
+
+}  // namespace swsph

@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/swsph.h, and rejects bad arguments on the host before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "swsph.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(swsph_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2505_14538_amd import swsph
+    return swsph
+
+
+def test_exports_every_declared_symbol(S):
+    names = declared_functions()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(S._lib, nm), nm
+    assert set(S.EXPORTS) == set(names)
+
+
+def test_version_and_defaults(S):
+    assert S.version() == 1
+    c = S.default_config()
+    assert c.eta == pytest.approx(1.2348) and c.eps == 2.0
+    assert c.gamma == pytest.approx(5.0 / 3.0) and c.alpha == 1.0 and c.beta == 3.0
+    assert c.h_max_iter == 40 and c.dtype == 0
+
+
+@pytest.mark.parametrize("field,val", [("eta", 0.0), ("eps", -1.0), ("gamma", 1.0),
+                                       ("alpha", -0.5), ("h_tol", 0.0), ("h_max_iter", 0),
+                                       ("dtype", 7), ("tile", 24), ("lds_cap", 100),
+                                       ("order", 3), ("flags", 0x4 | 0x8)])
+def test_plan_rejects_bad_config(S, field, val):
+    c = S.default_config()
+    setattr(c, field, val)
+    h = ctypes.c_void_p()
+    r = S._lib.swsph_plan_create(ctypes.byref(h), ctypes.byref(c))
+    assert r == -1
+    assert len(S._lib.swsph_last_error()) > 0
+
+
+def test_workspace_bytes_and_bad_boxes(S):
+    p = S.Plan()
+    out = ctypes.c_uint64()
+    bs = (ctypes.c_double * 1)(1.0)
+    assert S._lib.swsph_workspace_bytes(p.h, 4096, 1, None, bs, ctypes.byref(out)) == 0
+    small = out.value
+    assert S._lib.swsph_workspace_bytes(p.h, 1 << 20, 1, None, bs, ctypes.byref(out)) == 0
+    assert out.value > small
+    # counts must add up to n
+    bc = (ctypes.c_int64 * 2)(10, 20)
+    bs2 = (ctypes.c_double * 2)(1.0, 2.0)
+    assert S._lib.swsph_workspace_bytes(p.h, 31, 2, bc, bs2, ctypes.byref(out)) == -1
+    assert S._lib.swsph_workspace_bytes(p.h, 30, 2, bc, bs2, ctypes.byref(out)) == 0
+    bs2[1] = -1.0
+    assert S._lib.swsph_workspace_bytes(p.h, 30, 2, bc, bs2, ctypes.byref(out)) == -1
+    assert S._lib.swsph_workspace_bytes(p.h, -5, 1, None, bs, ctypes.byref(out)) == -1
+
+
+def test_calls_reject_bad_particles_on_host(S):
+    """Null arrays, missing box ids, unbound workspace: rejected before any
+    HIP call (this runs on a machine without a GPU)."""
+    p = S.Plan()
+    pc = S.ParticlesC()
+    pc.n = 100
+    pc.n_box = 1
+    bs = np.array([1.0])
+    pc.box_size = bs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ws = ctypes.c_void_p(256)
+    assert S._lib.swsph_bin(p.h, ctypes.byref(pc), ws, None) == -1      # null positions
+    pc.x = pc.y = pc.z = pc.vx = pc.vy = pc.vz = pc.m = 1024
+    pc.n_box = 2
+    assert S._lib.swsph_bin(p.h, ctypes.byref(pc), ws, None) == -1      # box ids missing
+    pc.n_box = 1
+    assert S._lib.swsph_bin(p.h, ctypes.byref(pc), ctypes.c_void_p(260), None) == -1  # alignment
+    d = S.DensityOut()
+    assert S._lib.swsph_density(p.h, ctypes.byref(pc), ctypes.byref(d), ws, None) == -1
+    d.h = d.rho = d.f = 4096
+    assert S._lib.swsph_density(p.h, ctypes.byref(pc), ctypes.byref(d), ws, None) == -3  # no bin
+    fo = S.ForceOut()
+    assert S._lib.swsph_force(p.h, ctypes.byref(pc), ctypes.byref(d), ctypes.byref(fo), ws,
+                              None) == -1                                  # u missing
+    st = S.Stats()
+    assert S._lib.swsph_read_stats(p.h, ws, ctypes.byref(st), None) == -3
+    # FIXED_H needs h
+    q = S.Plan(flags=S.FIXED_H)
+    assert S._lib.swsph_bin(q.h, ctypes.byref(pc), ws, None) == -1
