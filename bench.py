@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPH neighbour loops on one MI355X.
+
+Workload: the clustered 128^3 set -- 2,097,152 particles drawn from a
+lognormal density field (sigma_ln = 1.5, Gaussian-smoothed white noise on a
+64^3 grid) in a periodic unit box, u ~ U(0.5, 1.5), v ~ N(0, 0.1), float32.
+A step is one pass of the whole hot path on resident device data: binning
+(counting sort + task lists), density with Newton iteration on h, gradient,
+force.  Timed with HIP events on the library's stream (torch's current
+stream), whole steps between synchronisations.
+
+Metric: pair interactions per second of the density and force loops
+(useful pairs: r < H_i for density, r < max(H_i, H_j) for force) over the
+whole step time.  Reported alongside: per-loop rates, the fraction of the
+FP32 vector peak reached by the arithmetic of the useful pairs, the same
+step with one kernel launch per tile task (the per-task offload baseline),
+the roofline entry of the dominant kernel and the FP64 oracle on the host
+cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FLOPs per useful pair, counted on the arithmetic each loop performs for a
+# pair inside the support (FMA = 2, add/mul/min/max = 1, sqrt/rsqrt/rcp = 1).
+F_DENS = 55.0     # full density sums (n, dn/dh, rho, drho/dh, div v, curl v)
+F_NEWTON = 25.0   # each additional Newton sweep (n and dn/dh only)
+F_GRAD = 33.0
+F_FORCE = 67.0
+PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (packed FMA)
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(parts, budget_s=20.0):
+    """The FP64 oracle on the host cores: density (Newton) for every
+    particle, force for a random sample; pairs per second of both."""
+    from oracle import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    prm = O.Params(ncell=128)
+    t0 = time.time()
+    d = O.density(parts, prm)
+    t_d = time.time() - t0
+    P_d = float(np.sum(d["nngb"]))
+    rng = np.random.default_rng(5)
+    ns = 20000
+    idx = np.sort(rng.choice(parts.n, ns, replace=False))
+    t0 = time.time()
+    f = O.force(parts, d, prm, idx=idx)
+    t_f = time.time() - t0
+    P_f = float(np.sum(f["nint"][idx]))
+    rate = (P_d + P_f) / (t_d + t_f)
+    return {"value": rate, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle, cell-list mode: density with Newton on all %d particles "
+                      "(%.1f s) + force on %d random particles (%.1f s)" % (parts.n, t_d, ns, t_f)}
+
+
+def run(args):
+    import torch
+    from paper_2505_14538_amd import swsph as S
+    from paper_2505_14538_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    log("generating clustered workload")
+    parts = W.clustered()
+    dp = S.to_device(parts)
+    plan = S.Plan(flags=S.TIMING)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def step(pl):
+        pl.bin(dp)
+        d = pl.density(dp)
+        g = pl.gradient(dp, d)
+        f = pl.force(dp, d)
+        return d, g, f
+
+    for _ in range(args.warmup):
+        step(plan)
+    torch.cuda.synchronize()
+    plan.reset_timers()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        d, g, f = step(plan)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_step = ev0.elapsed_time(ev1) / 1e3 / args.steps
+    st = plan.stats()
+    if st["code"] != 0:
+        raise SystemExit("device status %s" % st)
+    kt = plan.kernel_times()   # ms per launch of the loop kernels (HIP events)
+    nngb = d["nngb"].to(torch.int64).sum().item()
+    nint = f["nint"].to(torch.int64).sum().item()
+    P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
+    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"]) / (args.steps + args.warmup)
+    value = (P_d + P_f) / t_step
+    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
+    frac_peak = flops / t_step / PEAK_FP32
+    log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
+
+    # per-task launch baseline (same tile bodies, one launch per task)
+    pt = S.Plan(flags=S.PER_TASK_LAUNCH)
+    step(pt)
+    torch.cuda.synchronize()
+    ev0.record()
+    step(pt)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_pt = ev0.elapsed_time(ev1) / 1e3
+    value_pt = (P_d + P_f) / t_pt
+    log("per-task launch step %.1f ms" % (t_pt * 1e3))
+
+    # roofline of the dominant kernel (largest share of the step)
+    dom = max(kt, key=lambda k: kt[k]["ms"] * kt[k]["launches"])
+    k_ms = kt[dom]["ms"]
+    per_launch_flops = {"density": P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON),
+                        "gradient": P_g * F_GRAD, "force": P_f * F_FORCE}[dom]
+    achieved = per_launch_flops / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
+                "kernel": "k_loop<%s> (loop kernel of the %s loop)" % (dom, dom),
+                "kernel_ms": k_ms}
+    res = {
+        "metric": "pair interactions/s (density+force), % FP32 peak; batched vs per-task launch",
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "clustered 128^3: 2,097,152 particles, lognormal field "
+                               "sigma_ln=1.5 on 64^3 grid, periodic unit box, FP32",
+                   "n": parts.n, "loops": "bin+density(Newton)+gradient+force"},
+        "pairs": {"density": P_d, "gradient": P_g, "force": P_f},
+        "rates": {k: {"pairs_per_s": {"density": P_d, "gradient": P_g, "force": P_f}[k] /
+                      (kt[k]["ms"] * 1e-3), "kernel_ms": kt[k]["ms"]} for k in kt},
+        "frac_fp32_peak": frac_peak,
+        "newton_sweeps_per_tile": sweeps,
+        "per_task_launch": {"value": value_pt, "ms_per_step": t_pt * 1e3,
+                            "batched_speedup": t_pt / t_step},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(parts)
+    print(json.dumps(res), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        raise SystemExit("this build runs on one GPU: --gpus must be 1 (the multi-GPU sharding "
+                         "of the loops is described in DESIGN.md but not built)")
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,6 +87,7 @@ typedef enum swsph_dtype { SWSPH_F32 = 0, SWSPH_F64 = 1 } swsph_dtype;
 #define SWSPH_NO_VISC          0x2u  /* force: viscosity off */
 #define SWSPH_PER_TASK_LAUNCH  0x4u  /* one kernel launch per tile task */
 #define SWSPH_FLAT_LAUNCH      0x8u  /* one launch, one wavefront per task, no queue */
+#define SWSPH_TIMING           0x10u /* record HIP events around every loop-kernel launch */
 
 /* Scheme constants and execution options.  swsph_config_default() fills
  * eta = 1.2348, eps = 2, gamma = 5/3, alpha = 1, beta = 3, h_tol = 2e-6,
@@ -246,6 +247,17 @@ int swsph_read_stats(swsph_plan* plan, const void* ws, swsph_stats* out, void* s
  * reuse the choice across processes (key: device, n, n_box, dtype). */
 int swsph_autotune(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream,
                    const char* cache_path);
+
+/* Per-launch duration of the loop kernels, from HIP events the library
+ * records on the call's stream around each loop-kernel launch when the plan
+ * has SWSPH_TIMING (index 0 density, 1 gradient, 2 force, 3 backward pair
+ * passes).  ms[k] = mean milliseconds per launch, launches[k] = launches
+ * timed since the last reset.  Synchronises the stream.  Without
+ * SWSPH_TIMING every entry is 0. */
+int swsph_kernel_times(swsph_plan* plan, double ms[4], uint64_t launches[4], void* stream);
+
+/* Forget the recorded kernel timings. */
+int swsph_reset_timers(swsph_plan* plan);
 
 /* The tuning the plan will use: tile, lds_cap, order, leaf_max. */
 int swsph_plan_get_tuning(const swsph_plan* plan, int32_t* tile, int32_t* lds_cap,

@@ -141,15 +141,48 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.g_out = take(2 * T * N);
     l.f_out = take(4 * T * N);
     l.f_int = take(4 * N);
-    l.adj = take(16 * T * N);
+    l.adj = take(32 * T * N);
     l.total = o;
     return SWSPH_OK;
 }
 
 }  // namespace
 
+// Pools of HIP event pairs, one list per loop kind.
+struct swsph::Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+    size_t used[4] = {0, 0, 0, 0};
+    ~Timer() {
+        for (auto& v : ev)
+            for (auto& p : v) {
+                (void)hipEventDestroy(p.first);
+                (void)hipEventDestroy(p.second);
+            }
+    }
+};
+
+void swsph::timer_begin(Timer* t, int loop, hipStream_t s) {
+    if (!t) return;
+    auto& v = t->ev[loop];
+    if (t->used[loop] == v.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        v.emplace_back(a, b);
+    }
+    (void)hipEventRecord(v[t->used[loop]].first, s);
+}
+
+void swsph::timer_end(Timer* t, int loop, hipStream_t s) {
+    if (!t) return;
+    auto& v = t->ev[loop];
+    if (t->used[loop] >= v.size()) return;
+    (void)hipEventRecord(v[t->used[loop]].second, s);
+    ++t->used[loop];
+}
+
 struct swsph_plan {
     swsph_config cfg;
+    swsph::Timer* timer = nullptr;
     int32_t tile, lds_cap, order, leaf_max;
     bool binned = false;
     void* ws = nullptr;
@@ -206,6 +239,7 @@ Scheme scheme_of(const swsph_plan* pl) {
     s.h_max_iter = pl->cfg.h_max_iter;
     s.flags = pl->cfg.flags;
     s.leaf_max = pl->leaf_max;
+    s.timer = pl->timer;
     return s;
 }
 
@@ -317,11 +351,13 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 512;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
+    if (cfg->flags & SWSPH_TIMING) pl->timer = new (std::nothrow) swsph::Timer();
     *out = pl;
     return SWSPH_OK;
 }
 
 int swsph_plan_destroy(swsph_plan* pl) {
+    if (pl) delete pl->timer;
     delete pl;
     return SWSPH_OK;
 }
@@ -474,6 +510,33 @@ int swsph_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_ou
     return hip_check(hipGetLastError(), "force");
 }
 
+int swsph_kernel_times(swsph_plan* pl, double ms[4], uint64_t launches[4], void* stream) {
+    if (!pl || !ms || !launches) return fail(SWSPH_E_ARG, "plan, ms and launches are required");
+    for (int k = 0; k < 4; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    if (!pl->timer) return SWSPH_OK;
+    int r = hip_check(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    if (r) return r;
+    for (int k = 0; k < 4; ++k) {
+        double tot = 0.0;
+        for (size_t i = 0; i < pl->timer->used[k]; ++i) {
+            float e = 0.f;
+            if (hipEventElapsedTime(&e, pl->timer->ev[k][i].first, pl->timer->ev[k][i].second) ==
+                hipSuccess)
+                tot += e;
+        }
+        launches[k] = pl->timer->used[k];
+        ms[k] = launches[k] ? tot / (double)launches[k] : 0.0;
+    }
+    return SWSPH_OK;
+}
+
+int swsph_reset_timers(swsph_plan* pl) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    if (pl->timer)
+        for (int k = 0; k < 4; ++k) pl->timer->used[k] = 0;
+    return SWSPH_OK;
+}
+
 int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* stream) {
     if (!pl || !ws || !out) return fail(SWSPH_E_ARG, "plan, ws and out are required");
     if (!pl->binned || ws != pl->ws) return fail(SWSPH_E_STATE, "no bin on this workspace");
@@ -528,8 +591,33 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
 
 int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
                          const swsph_force_grad* g, swsph_input_grad* gi, void* ws, void* stream) {
-    (void)pl; (void)p; (void)d; (void)g; (void)gi; (void)ws; (void)stream;
-    return fail(SWSPH_E_ARG, "swsph_force_backward: not available in this build");
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f || !d->rho_dh || !d->wcount || !d->wcount_dh)))
+        return fail(SWSPH_E_ARG, "backward needs density h, rho, f, rho_dh, wcount, wcount_dh");
+    if (!g || (p->n > 0 && (!g->gax || !g->gay || !g->gaz || !g->gdudt)))
+        return fail(SWSPH_E_ARG, "backward needs dL/da and dL/d(du/dt)");
+    if (!gi) return fail(SWSPH_E_ARG, "input gradient output is NULL");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int64_t n = b.n;
+    void* dst[8] = {gi->gx, gi->gy, gi->gz, gi->gvx, gi->gvy, gi->gvz, gi->gu, gi->gm};
+    const int src[8] = {7, 8, 9, 10, 11, 12, 14, 13};  // adjoint scratch arrays (binned order)
+    if (pl->cfg.dtype == SWSPH_F64) {
+        r = launch_backward<double>(b, sc, g, d, pl->lds_cap, s);
+        for (int k = 0; k < 8; ++k)
+            launch_unsort<double>(n, b.rank, (double*)b.adj + src[k] * n, dst[k], s);
+    } else {
+        r = launch_backward<float>(b, sc, g, d, pl->lds_cap, s);
+        for (int k = 0; k < 8; ++k)
+            launch_unsort<float>(n, b.rank, (float*)b.adj + src[k] * n, dst[k], s);
+    }
+    if (r) return fail(SWSPH_E_HIP, "backward kernel launch failed");
+    return hip_check(hipGetLastError(), "force_backward");
 }
 
 int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream,

@@ -6,12 +6,18 @@
 
 namespace swsph {
 
+// Events around loop-kernel launches (SWSPH_TIMING); owned by the plan.
+struct Timer;
+void timer_begin(Timer* t, int loop, hipStream_t s);
+void timer_end(Timer* t, int loop, hipStream_t s);
+
 // Scheme constants and options passed to the loop kernels.
 struct Scheme {
     double eta, eps, gamma, alpha, beta, h_tol;
     int32_t h_max_iter;
     uint32_t flags;
     int32_t leaf_max;
+    Timer* timer;   // nullable
 };
 
 // Device pointers of one bin (all inside the workspace).

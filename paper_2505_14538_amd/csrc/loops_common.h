@@ -1,0 +1,291 @@
+// loops_common.h -- shared pieces of the loop kernels (forward and adjoint):
+// per-wavefront LDS layout, kernel arguments, the staging of a tile's
+// j-particles from its task list, and M4 kernel pieces.
+#pragma once
+
+#include "launch.h"
+#include "search.h"
+
+namespace swsph {
+
+constexpr int WPB = 4;  // wavefronts per workgroup
+
+template <typename T, int CAP, int NV>
+struct WaveMem {
+    V4<T> s[NV][CAP];          // staged j-particles
+    int32_t lbeg[WAVE];        // current batch of task-list leaves
+    int32_t lpre[WAVE + 1];
+    int32_t lshift[WAVE];
+};
+
+template <typename T>
+struct KArgs {
+    const BoxInfo* boxtab;
+    const Tile* tiles;
+    const int32_t* order;
+    int32_t n_tiles;
+    int32_t task;              // per-task launch: the task to run
+    const int32_t* leaf_cnt;
+    const int32_t* leaf_off;
+    const int2* leaves;
+    int64_t leaf_cap;
+    float* trad;
+    int32_t* tflag;
+    const V4<T>* pos4;
+    const V4<T>* vel4;
+    T* hs;
+    const V4<T>* dens4;
+    const V4<T>* aux4;         // adjoint passes: per-particle staging data
+    T* out;                    // sorted outputs, arrays of n
+    int32_t* iout;             // sorted int outputs, arrays of n
+    int64_t n;
+    Counters* cnt;
+    unsigned long long* queue;
+    T eta, eps, gamma, alpha, beta, h_tol;
+    int32_t h_max_iter;
+    uint32_t flags;
+    int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
+};
+
+// loop kinds: forward loops and the three pair passes of the adjoint
+enum { L_DENS = 0, L_GRAD = 1, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
+
+template <int LK> struct LoopNV;
+template <> struct LoopNV<L_DENS> { static constexpr int NV = 2; };
+template <> struct LoopNV<L_GRAD> { static constexpr int NV = 3; };
+template <> struct LoopNV<L_FORCE> { static constexpr int NV = 4; };
+template <> struct LoopNV<L_ADJA> { static constexpr int NV = 5; };
+template <> struct LoopNV<L_ADJC> { static constexpr int NV = 2; };
+template <> struct LoopNV<L_ADJD> { static constexpr int NV = 2; };
+
+// cull with the symmetric criterion r < max(H_i, H_j)?
+template <int LK> struct Symmetric { static constexpr bool value = LK >= L_FORCE; };
+
+template <typename T> __device__ __forceinline__ T int_as(int32_t v);
+template <> __device__ __forceinline__ float int_as<float>(int32_t v) { return __int_as_float(v); }
+template <> __device__ __forceinline__ double int_as<double>(int32_t v) { return (double)v; }
+template <typename T> __device__ __forceinline__ int32_t as_int(T v);
+template <> __device__ __forceinline__ int32_t as_int<float>(float v) { return __float_as_int(v); }
+template <> __device__ __forceinline__ int32_t as_int<double>(double v) { return (int32_t)v; }
+
+// Stream the j-particles of tile t's task list through the lanes, cull them
+// against the tile box (radius R, or the j-particle's own support for the
+// force loop), stage survivors in LDS; flush(nsurv) is called whenever the
+// buffer could overflow (the buffer is empty afterwards).  Returns the
+// number of staged survivors left for the caller.
+template <int LK, typename T, int CAP, class WM, class Flush>
+__device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
+                          T R2, int& flushes, Flush&& flush) {
+    const int lane = lane_id();
+    const int64_t off = a.leaf_off[t];
+    int64_t nl = a.leaf_cnt[t];
+    if (off + nl > a.leaf_cap) nl = a.leaf_cap > off ? a.leaf_cap - off : 0;
+    const T L = (T)bi.L;
+    int nsurv = 0;
+    flushes = 0;
+    for (int64_t lb = 0; lb < nl; lb += WAVE) {
+        const int nb = (int)min((int64_t)WAVE, nl - lb);
+        int32_t beg = 0, num = 0;
+        int sh = 13;
+        if (lane < nb) unpack_leaf(a.leaves[off + lb + lane], beg, num, sh);
+        int total;
+        const int e = wave_excl_scan(num, total);
+        m.lbeg[lane] = beg;
+        m.lpre[lane] = e;
+        m.lshift[lane] = sh;
+        if (lane == 0) m.lpre[WAVE] = total;
+        wave_sync();
+        for (int base = 0; base < total; base += WAVE) {
+            if (nsurv + WAVE > CAP) {
+                flush(nsurv);
+                nsurv = 0;
+                ++flushes;
+            }
+            const int v = base + lane;
+            bool pass = false;
+            V4<T> pa;
+            T xs = 0, ys = 0, zs = 0;
+            int j = 0;
+            if (v < total) {
+                int lo = 0, hi = nb - 1;
+                while (lo < hi) {  // last leaf whose prefix is <= v
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                j = m.lbeg[lo] + (v - m.lpre[lo]);
+                if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid task list
+                int sx, sy, sz;
+                shift_of(m.lshift[lo], sx, sy, sz);
+                pa = a.pos4[j];
+                xs = pa.x + (T)sx * L;
+                ys = pa.y + (T)sy * L;
+                zs = pa.z + (T)sz * L;
+                const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+                const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+                const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+                const T d2 = dist2_unfused(gx, gy, gz);
+                T crit = R2;
+                if (Symmetric<LK>::value) {
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    crit = max(crit, mul_unfused(Hj, Hj));
+                }
+                pass = d2 < crit;
+            }
+            const unsigned long long pm = ballot(pass);
+            if (pass) {
+                const int k = nsurv + mbcnt(pm);
+                const V4<T> va = a.vel4[j];
+                if (LK == L_DENS) {
+                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
+                } else if (LK == L_GRAD) {
+                    const V4<T> da = a.dens4[j];  // (rho, f, c, A)
+                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                    m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
+                } else if (LK == L_FORCE) {
+                    const V4<T> da = a.dens4[j];
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                    m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
+                    m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
+                } else if (LK == L_ADJA) {
+                    const V4<T> da = a.dens4[j];   // (rho, f, c, A)
+                    const V4<T> wj = a.aux4[j];    // (dL/dax, dL/day, dL/daz, dL/ddu)
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                    m.s[2][k] = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
+                    m.s[3][k] = V4<T>{da.x, wj.x, wj.y, wj.z};
+                    m.s[4][k] = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
+                } else {
+                    // density adjoint: (m, rho_bar, rho'_bar, 1/H); implicit h: (lambda h^3, 1/H, idx, 0)
+                    const T Hj = mul_unfused(a.eps, a.hs[j]);
+                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                    m.s[1][k] = a.aux4[j];
+                }
+            }
+            nsurv += __popcll(pm);
+            wave_sync();
+        }
+    }
+    return nsurv;
+}
+
+// ---------------------------------------------------------------- kernels
+// M4 pieces on q = r/H:  w, s1 = 3w + q w', g = w'/q  (all finite at q = 0).
+
+template <typename T>
+__device__ __forceinline__ void m4_terms(T q, T inv_q, T& w, T& s1, T& g) {
+    const T t = (T)1 - q;
+    const T q2 = q * q;
+    if (q < (T)0.5) {
+        w = (T)1 + q2 * ((T)6 * q - (T)6);
+        s1 = (T)3 + q2 * ((T)36 * q - (T)30);
+        g = (T)18 * q - (T)12;
+    } else {
+        const T t2 = t * t;
+        w = (T)2 * t2 * t;
+        s1 = (T)6 * t2 * ((T)1 - (T)2 * q);
+        g = (T)-6 * t2 * inv_q;
+    }
+}
+// w'(q)
+template <typename T> __device__ __forceinline__ T m4_dw(T q) {
+    const T t = (T)1 - q;
+    return q < (T)0.5 ? q * ((T)18 * q - (T)12) : (T)-6 * t * t;
+}
+
+__device__ __forceinline__ TileGeom geom_of(const Tile& tl) {
+    TileGeom g;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
+    return g;
+}
+
+
+template <typename T>
+inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
+    KArgs<T> a;
+    a.boxtab = b.boxtab;
+    a.tiles = b.tiles;
+    a.order = b.order;
+    a.n_tiles = b.n_tiles;
+    a.task = 0;
+    a.leaf_cnt = b.leaf_cnt;
+    a.leaf_off = b.leaf_off;
+    a.leaves = b.leaves;
+    a.leaf_cap = b.leaf_cap;
+    a.trad = b.trad;
+    a.tflag = b.tflag;
+    a.pos4 = (const V4<T>*)b.pos4;
+    a.vel4 = (const V4<T>*)b.vel4;
+    a.hs = (T*)b.hs;
+    a.dens4 = (const V4<T>*)b.dens4;
+    a.aux4 = nullptr;
+    a.out = nullptr;
+    a.iout = nullptr;
+    a.n = b.n;
+    a.cnt = b.cnt;
+    a.queue = nullptr;
+    a.eta = (T)sc.eta;
+    a.eps = (T)sc.eps;
+    a.gamma = (T)sc.gamma;
+    a.alpha = (T)sc.alpha;
+    a.beta = (T)sc.beta;
+    a.h_tol = (T)sc.h_tol;
+    a.h_max_iter = sc.h_max_iter;
+    a.flags = sc.flags;
+    a.fixup = 0;
+    return a;
+}
+
+// Launch a loop kernel (k(args, mode)) in one of the three modes: the
+// persistent queue (grid = resident workgroups), flat (a wavefront per task)
+// or one launch per task.
+template <int LK, typename T, int CAP>
+int launch_with(void (*kern)(KArgs<T>, int), KArgs<T> a, int mode, int queue_slot,
+                hipStream_t s) {
+    constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
+    const size_t shm = WMS * WPB;
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm) != hipSuccess)
+            return -1;
+        attr_set = true;
+    }
+    if (a.n_tiles <= 0) return 0;
+    a.queue = &a.cnt->queue[queue_slot];
+    if (mode == MODE_QUEUE) {
+        launch_fill_u32(a.queue, 2, 0u, s);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WPB * WAVE,
+                                                         shm) != hipSuccess)
+            per_cu = 1;
+        if (per_cu < 1) per_cu = 1;
+        int64_t blocks = (int64_t)per_cu * device_cu_count();
+        const int64_t need = (a.n_tiles + WPB - 1) / WPB;
+        if (blocks > need) blocks = need;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, a, (int)MODE_QUEUE);
+    } else if (mode == MODE_FLAT) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)((a.n_tiles + WPB - 1) / WPB)), dim3(WPB * WAVE),
+                           shm, s, a, (int)MODE_FLAT);
+    } else {
+        for (int t = 0; t < a.n_tiles; ++t) {
+            a.task = t;
+            hipLaunchKernelGGL(kern, dim3(1), dim3(WAVE), WMS, s, a, (int)MODE_PER_TASK);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+template <int LK, typename T, int CAP>
+constexpr bool fits() {
+    return WPB * sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>) <= LDS_LIMIT;
+}
+
+}  // namespace swsph

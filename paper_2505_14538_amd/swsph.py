@@ -30,6 +30,7 @@ FIXED_H = 0x1
 NO_VISC = 0x2
 PER_TASK_LAUNCH = 0x4
 FLAT_LAUNCH = 0x8
+TIMING = 0x10
 
 ST_CAPACITY, ST_REACH, ST_NEWTON, ST_DOMAIN = 0x1, 0x2, 0x4, 0x8
 
@@ -116,11 +117,14 @@ _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
 _lib.swsph_autotune.argtypes = [_vp, _P(ParticlesC), _vp, _vp, ctypes.c_char_p]
 _lib.swsph_plan_get_tuning.argtypes = [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
                                        _P(ctypes.c_int32), _P(ctypes.c_int32)]
+_lib.swsph_kernel_times.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_uint64), _vp]
+_lib.swsph_reset_timers.argtypes = [_vp]
 
 EXPORTS = ["swsph_version", "swsph_last_error", "swsph_config_default", "swsph_plan_create",
            "swsph_plan_destroy", "swsph_workspace_bytes", "swsph_bin", "swsph_density",
            "swsph_gradient", "swsph_force", "swsph_force_backward", "swsph_step",
-           "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning"]
+           "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
+           "swsph_kernel_times", "swsph_reset_timers"]
 
 
 class SwsphError(RuntimeError):
@@ -355,6 +359,17 @@ class Plan:
         d["code"] = r
         return d
 
+    def kernel_times(self) -> Dict[str, Dict[str, float]]:
+        """Mean ms per launch of each loop kernel (plan created with TIMING)."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_uint64 * 4)()
+        _check(_lib.swsph_kernel_times(self.h, ms, n, _stream()))
+        names = ("density", "gradient", "force", "backward")
+        return {names[k]: {"ms": ms[k], "launches": int(n[k])} for k in range(4) if n[k] > 0}
+
+    def reset_timers(self):
+        _check(_lib.swsph_reset_timers(self.h))
+
     def autotune(self, p: DeviceParticles, cache_path: Optional[str] = None):
         self.ensure_workspace(p)
         pc = p.c()
@@ -372,3 +387,57 @@ class Plan:
 def host(d: Dict[str, object]) -> Dict[str, np.ndarray]:
     """Copy a dict of device tensors to numpy."""
     return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in d.items()}
+
+
+# ------------------------------------------------------------------ autograd
+
+class _SPHForce:
+    """torch.autograd.Function wrapper (built lazily so importing this module
+    does not require torch)."""
+
+    fn = None
+
+    @classmethod
+    def get(cls):
+        if cls.fn is None:
+            import torch
+
+            class SPHForce(torch.autograd.Function):
+                """(x, y, z, vx, vy, vz, u, m) -> (ax, ay, az, du/dt): bin, density
+                (Newton on h) and force in the forward pass; the hand-written adjoint
+                (swsph_force_backward) in the backward pass.  Only per-particle
+                density results are saved."""
+
+                @staticmethod
+                def forward(ctx, plan, box_size, box_count, box_id, x, y, z, vx, vy, vz, u, m):
+                    dp = DeviceParticles(x.detach(), y.detach(), z.detach(), vx.detach(),
+                                         vy.detach(), vz.detach(), u.detach(), m.detach(),
+                                         np.asarray(box_size), np.asarray(box_count), box_id)
+                    plan.bin(dp)
+                    d = plan.density(dp)
+                    f = plan.force(dp, d)
+                    ctx.plan = plan
+                    ctx.dp = dp
+                    ctx.d = {k: d[k] for k in ("h", "rho", "f", "rho_dh", "wcount", "wcount_dh")}
+                    return f["ax"], f["ay"], f["az"], f["dudt"]
+
+                @staticmethod
+                def backward(ctx, gax, gay, gaz, gdu):
+                    zeros = lambda g: torch.zeros_like(ctx.dp.x) if g is None else g.contiguous()
+                    plan, dp = ctx.plan, ctx.dp
+                    plan.bin(dp)
+                    gi = plan.force_backward(dp, ctx.d, zeros(gax), zeros(gay), zeros(gaz),
+                                             zeros(gdu))
+                    return (None, None, None, None, gi["gx"], gi["gy"], gi["gz"], gi["gvx"],
+                            gi["gvy"], gi["gvz"], gi["gu"], gi["gm"])
+
+            cls.fn = SPHForce
+        return cls.fn
+
+
+def sph_force(plan: Plan, x, y, z, vx, vy, vz, u, m, box_size=(1.0,), box_count=None,
+              box_id=None):
+    """Differentiable accelerations and du/dt of particles in periodic boxes."""
+    bc = np.array([x.shape[0]], dtype=np.int64) if box_count is None else np.asarray(box_count)
+    return _SPHForce.get().apply(plan, np.asarray(box_size, dtype=np.float64), bc, box_id,
+                                 x, y, z, vx, vy, vz, u, m)
