@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(parts, budget_s=20.0):
+def cpu_baseline(parts):
     """The FP64 oracle on the host cores: density (Newton) for every
     particle, force for a random sample; pairs per second of both."""
     from oracle import oracle as O
@@ -53,7 +53,7 @@ def cpu_baseline(parts, budget_s=20.0):
     t_d = time.time() - t0
     P_d = float(np.sum(d["nngb"]))
     rng = np.random.default_rng(5)
-    ns = 20000
+    ns = 200000
     idx = np.sort(rng.choice(parts.n, ns, replace=False))
     t0 = time.time()
     f = O.force(parts, d, prm, idx=idx)
@@ -170,8 +170,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        raise SystemExit("this build runs on one GPU: --gpus must be 1 (the multi-GPU sharding "
-                         "of the loops is described in DESIGN.md but not built)")
+        raise SystemExit("bench.py runs on one GPU only: --gpus must be 1 (sharding the loops "
+                         "over several GPUs is not implemented)")
     run(args)
 
 

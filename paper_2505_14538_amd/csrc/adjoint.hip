@@ -59,8 +59,10 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -79,96 +81,103 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     const T alpha = a.alpha, beta = a.beta;
     T gx = 0, gy = 0, gz = 0, gvx = 0, gvy = 0, gvz = 0;
     T gm = 0, gA = 0, gf = 0, gc = 0, grho = 0, gh = 0;
-    auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> s0 = m.s[0][k];
-            const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            const T H2j = s0.w;
-            const int jj = as_int<T>(m.s[4][k].y);
-            if (!(r2 < max(H2, H2j)) || jj == i || !(r2 > (T)0)) continue;
-            const V4<T> s1 = m.s[1][k];  // v_j, c_j
-            const V4<T> s2 = m.s[2][k];  // m_j, A_j, f_j, 1/H_j
-            const V4<T> s3 = m.s[3][k];  // rho_j, w_j
-            const T ej = m.s[4][k].x;
-            const T inv_r = fast_rsqrt(r2);
-            const T r = r2 * inv_r;
-            const T ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
-            // kernel at h_i: dW/dr, d2W/dr2, d2W/dh dr
-            T gi = 0, gri = 0, ghi = 0;
-            if (r2 < H2) {
-                const T q = r * invH, dw = m4_dw(q), d2 = m4_d2w(q);
-                gi = cn * iH4 * dw;
-                gri = cn * iH5 * d2;
-                ghi = -cn * eps * iH5 * ((T)4 * dw + q * d2);
-            }
-            T gj = 0, grj = 0;
-            if (r2 < H2j) {
-                const T ihj = s2.w;
-                const T q = r * ihj, ih4 = ihj * ihj * ihj * ihj;
-                gj = cn * ih4 * m4_dw(q);
-                grj = cn * ih4 * ihj * m4_d2w(q);
-            }
-            const T mj = s2.x, Aj = s2.y, fj = s2.z, rhoj = s3.x;
-            const T vxr = vi.x - s1.x, vyr = vi.y - s1.y, vzr = vi.z - s1.z;
-            const T vdote = vxr * ex + vyr * ey + vzr * ez;
-            const bool neg = vdote < (T)0;
-            const T mu = neg ? vdote : (T)0;
-            T nu = 0, dnu_dmu = 0, dnu_dc = 0, dnu_drho = 0;
-            if (visc) {
-                const T rs = rhoi + rhoj;
-                const T vs = ci + s1.w - beta * mu;
-                nu = -alpha * mu * vs / rs;
-                dnu_dmu = -alpha * (vs - beta * mu) / rs;
-                dnu_dc = -alpha * mu / rs;
-                dnu_drho = -nu / rs;
-            }
-            const T Gs = fi * gi + fj * gj;
-            const T Fn = Ai * gi + Aj * gj + (T)0.5 * nu * Gs;
-            // ordered pair (i, j): weights of i, neighbour mass m_j
-            const T p1 = wi.x * ex + wi.y * ey + wi.z * ez;
-            const T Dn1 = Ai * gi + (T)0.25 * nu * Gs;
-            const T k1 = (T)-0.5 * p1 + (T)0.25 * wi.w * vdote;
-            gA += mj * gi * (wi.w * vdote - p1);
-            gf += mj * nu * gi * k1;
-            const T nub1 = mj * Gs * k1;
-            const T gbi1 = mj * (-p1 * (Ai + (T)0.5 * nu * fi) + wi.w * vdote * (Ai + (T)0.25 * nu * fi));
-            const T gbj1 = mj * (-p1 * (Aj + (T)0.5 * nu * fj) + wi.w * vdote * (T)0.25 * nu * fj);
-            const T vdb1 = wi.w * mj * Dn1 + (neg ? nub1 * dnu_dmu : (T)0);
-            // ordered pair (j, i): weights of j, neighbour mass m_i, unit vector -e
-            const T p2 = -(s3.y * ex + s3.z * ey + s3.w * ez);
-            const T Dn2 = Aj * gj + (T)0.25 * nu * Gs;
-            const T k2 = (T)-0.5 * p2 + (T)0.25 * ej * vdote;
-            gA += -p2 * mi * gi;
-            gf += mi * nu * gi * k2;
-            const T nub2 = mi * Gs * k2;
-            const T gbi2 = mi * (-p2 * (Ai + (T)0.5 * nu * fi) + ej * vdote * (T)0.25 * nu * fi);
-            const T gbj2 = mi * (-p2 * (Aj + (T)0.5 * nu * fj) + ej * vdote * (Aj + (T)0.25 * nu * fj));
-            const T vdb2 = ej * mi * Dn2 + (neg ? nub2 * dnu_dmu : (T)0);
-            gm += -p2 * Fn + ej * Dn2 * vdote;
-            gc += (nub1 + nub2) * dnu_dc;
-            grho += (nub1 + nub2) * dnu_drho;
-            gh += (gbi1 + gbi2) * ghi;
-            // geometry: r (through the kernel derivatives) and the unit vector
-            const T rb = (gbi1 + gbi2) * gri + (gbj1 + gbj2) * grj;
-            const T vdb = vdb1 + vdb2;
-            const T Ex = -mj * Fn * wi.x + mi * Fn * s3.y + vdb * vxr;
-            const T Ey = -mj * Fn * wi.y + mi * Fn * s3.z + vdb * vyr;
-            const T Ez = -mj * Fn * wi.z + mi * Fn * s3.w + vdb * vzr;
-            const T Ee = Ex * ex + Ey * ey + Ez * ez;
-            gx += rb * ex + (Ex - Ee * ex) * inv_r;
-            gy += rb * ey + (Ey - Ee * ey) * inv_r;
-            gz += rb * ez + (Ez - Ee * ez) * inv_r;
-            gvx += vdb * ex;
-            gvy += vdb * ey;
-            gvz += vdb * ez;
-        }
+    // pairs with r = 0 (the self pair, coincident particles) contribute nothing
+    auto test = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
+        return act && r2 < max(H2, s0.w) && r2 > (T)0;
     };
+    auto body = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const T H2j = s0.w;
+        const V4<T> s1 = m.s[1][k];  // v_j, c_j
+        const V4<T> s2 = m.s[2][k];  // m_j, A_j, f_j, 1/H_j
+        const V4<T> s3 = m.s[3][k];  // rho_j, w_j
+        const T ej = m.s[4][k].x;
+        const T inv_r = fast_rsqrt(r2);
+        const T r = r2 * inv_r;
+        const T ex = dx * inv_r, ey = dy * inv_r, ez = dz * inv_r;
+        // kernel at h_i: dW/dr, d2W/dr2, d2W/dh dr
+        T gi = 0, gri = 0, ghi = 0;
+        if (r2 < H2) {
+            const T q = r * invH, dw = m4_dw(q), d2 = m4_d2w(q);
+            gi = cn * iH4 * dw;
+            gri = cn * iH5 * d2;
+            ghi = -cn * eps * iH5 * ((T)4 * dw + q * d2);
+        }
+        T gj = 0, grj = 0;
+        if (r2 < H2j) {
+            const T ihj = s2.w;
+            const T q = r * ihj, ih4 = ihj * ihj * ihj * ihj;
+            gj = cn * ih4 * m4_dw(q);
+            grj = cn * ih4 * ihj * m4_d2w(q);
+        }
+        const T mj = s2.x, Aj = s2.y, fj = s2.z, rhoj = s3.x;
+        const T vxr = vi.x - s1.x, vyr = vi.y - s1.y, vzr = vi.z - s1.z;
+        const T vdote = vxr * ex + vyr * ey + vzr * ez;
+        const bool neg = vdote < (T)0;
+        const T mu = neg ? vdote : (T)0;
+        T nu = 0, dnu_dmu = 0, dnu_dc = 0, dnu_drho = 0;
+        if (visc) {
+            const T rs = rhoi + rhoj;
+            const T vs = ci + s1.w - beta * mu;
+            nu = -alpha * mu * vs / rs;
+            dnu_dmu = -alpha * (vs - beta * mu) / rs;
+            dnu_dc = -alpha * mu / rs;
+            dnu_drho = -nu / rs;
+        }
+        const T Gs = fi * gi + fj * gj;
+        const T Fn = Ai * gi + Aj * gj + (T)0.5 * nu * Gs;
+        // ordered pair (i, j): weights of i, neighbour mass m_j
+        const T p1 = wi.x * ex + wi.y * ey + wi.z * ez;
+        const T Dn1 = Ai * gi + (T)0.25 * nu * Gs;
+        const T k1 = (T)-0.5 * p1 + (T)0.25 * wi.w * vdote;
+        gA += mj * gi * (wi.w * vdote - p1);
+        gf += mj * nu * gi * k1;
+        const T nub1 = mj * Gs * k1;
+        const T gbi1 = mj * (-p1 * (Ai + (T)0.5 * nu * fi) + wi.w * vdote * (Ai + (T)0.25 * nu * fi));
+        const T gbj1 = mj * (-p1 * (Aj + (T)0.5 * nu * fj) + wi.w * vdote * (T)0.25 * nu * fj);
+        const T vdb1 = wi.w * mj * Dn1 + (neg ? nub1 * dnu_dmu : (T)0);
+        // ordered pair (j, i): weights of j, neighbour mass m_i, unit vector -e
+        const T p2 = -(s3.y * ex + s3.z * ey + s3.w * ez);
+        const T Dn2 = Aj * gj + (T)0.25 * nu * Gs;
+        const T k2 = (T)-0.5 * p2 + (T)0.25 * ej * vdote;
+        gA += -p2 * mi * gi;
+        gf += mi * nu * gi * k2;
+        const T nub2 = mi * Gs * k2;
+        const T gbi2 = mi * (-p2 * (Ai + (T)0.5 * nu * fi) + ej * vdote * (T)0.25 * nu * fi);
+        const T gbj2 = mi * (-p2 * (Aj + (T)0.5 * nu * fj) + ej * vdote * (Aj + (T)0.25 * nu * fj));
+        const T vdb2 = ej * mi * Dn2 + (neg ? nub2 * dnu_dmu : (T)0);
+        gm += -p2 * Fn + ej * Dn2 * vdote;
+        gc += (nub1 + nub2) * dnu_dc;
+        grho += (nub1 + nub2) * dnu_drho;
+        gh += (gbi1 + gbi2) * ghi;
+        // geometry: r (through the kernel derivatives) and the unit vector
+        const T rb = (gbi1 + gbi2) * gri + (gbj1 + gbj2) * grj;
+        const T vdb = vdb1 + vdb2;
+        const T Ex = -mj * Fn * wi.x + mi * Fn * s3.y + vdb * vxr;
+        const T Ey = -mj * Fn * wi.y + mi * Fn * s3.z + vdb * vyr;
+        const T Ez = -mj * Fn * wi.z + mi * Fn * s3.w + vdb * vzr;
+        const T Ee = Ex * ex + Ey * ey + Ez * ez;
+        gx += rb * ex + (Ex - Ee * ex) * inv_r;
+        gy += rb * ey + (Ey - Ee * ey) * inv_r;
+        gz += rb * ez + (Ez - Ee * ez) * inv_r;
+        gvx += vdb * ex;
+        gvy += vdb * ey;
+        gvz += vdb * ez;
+    };
+    auto sweep = [&](int ns) { pair_loop(m, ns, js, S, test, body); };
     int flushes = 0;
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJA, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    if (act) {
+    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
+    gvx = stream_sum(gvx, T_i); gvy = stream_sum(gvy, T_i); gvz = stream_sum(gvz, T_i);
+    gm = stream_sum(gm, T_i); gA = stream_sum(gA, T_i); gf = stream_sum(gf, T_i);
+    gc = stream_sum(gc, T_i); grho = stream_sum(grho, T_i); gh = stream_sum(gh, T_i);
+    if (lead) {
         AdjPtrs<T> J{a.out, a.n};
         J.arr(AJ_GX)[i] = gx;
         J.arr(AJ_GX + 1)[i] = gy;
@@ -192,8 +201,10 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const T h = a.hs[i];
@@ -208,47 +219,52 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const V4<T> ai = a.aux4[i];  // (m_i, rho_bar_i, rho'_bar_i, 1/H_i)
     const T rb = ai.y, rpb = ai.z, mi = pi.w;
     T gx = 0, gy = 0, gz = 0, gm = 0, gh = 0;
-    auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> s0 = m.s[0][k];
-            const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            const bool own = r2 < H2, rev = act && r2 < s0.w;
-            if (!own && !rev) continue;
-            const V4<T> s1 = m.s[1][k];  // (m_j, rho_bar_j, rho'_bar_j, 1/H_j)
-            const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
-            const T r = r2 * inv_r;
-            T sx = 0;
-            if (own) {
-                const T q = r * invH, w = m4_w(q), dw = m4_dw(q), d2 = m4_d2w(q);
-                const T Wh = -cn * eps * iH4 * ((T)3 * w + q * dw);
-                const T Whh = cn * eps * eps * iH5 * ((T)12 * w + (T)8 * q * dw + q * q * d2);
-                const T Wr = cn * iH4 * dw;
-                const T Wrh = -cn * eps * iH5 * ((T)4 * dw + q * d2);
-                gh += s1.x * (rb * Wh + rpb * Whh);
-                sx += s1.x * (rb * Wr + rpb * Wrh);
-            }
-            if (rev) {
-                const T ihj = s1.w;
-                const T q = r * ihj, w = m4_w(q), dw = m4_dw(q), d2 = m4_d2w(q);
-                const T ih3 = ihj * ihj * ihj, ih4 = ih3 * ihj, ih5 = ih4 * ihj;
-                const T Wj = cn * ih3 * w;
-                const T Whj = -cn * eps * ih4 * ((T)3 * w + q * dw);
-                const T Wrj = cn * ih4 * dw;
-                const T Wrhj = -cn * eps * ih5 * ((T)4 * dw + q * d2);
-                gm += s1.y * Wj + s1.z * Whj;
-                sx += mi * (s1.y * Wrj + s1.z * Wrhj);
-            }
-            gx += sx * dx * inv_r;
-            gy += sx * dy * inv_r;
-            gz += sx * dz * inv_r;
-        }
+    auto test = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
+        return r2 < H2 || (act && r2 < s0.w);
     };
+    auto body = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const bool own = r2 < H2, rev = act && r2 < s0.w;
+        const V4<T> s1 = m.s[1][k];  // (m_j, rho_bar_j, rho'_bar_j, 1/H_j)
+        const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
+        const T r = r2 * inv_r;
+        T sx = 0;
+        if (own) {
+            const T q = r * invH, w = m4_w(q), dw = m4_dw(q), d2 = m4_d2w(q);
+            const T Wh = -cn * eps * iH4 * ((T)3 * w + q * dw);
+            const T Whh = cn * eps * eps * iH5 * ((T)12 * w + (T)8 * q * dw + q * q * d2);
+            const T Wr = cn * iH4 * dw;
+            const T Wrh = -cn * eps * iH5 * ((T)4 * dw + q * d2);
+            gh += s1.x * (rb * Wh + rpb * Whh);
+            sx += s1.x * (rb * Wr + rpb * Wrh);
+        }
+        if (rev) {
+            const T ihj = s1.w;
+            const T q = r * ihj, w = m4_w(q), dw = m4_dw(q), d2 = m4_d2w(q);
+            const T ih3 = ihj * ihj * ihj, ih4 = ih3 * ihj, ih5 = ih4 * ihj;
+            const T Wj = cn * ih3 * w;
+            const T Whj = -cn * eps * ih4 * ((T)3 * w + q * dw);
+            const T Wrj = cn * ih4 * dw;
+            const T Wrhj = -cn * eps * ih5 * ((T)4 * dw + q * d2);
+            gm += s1.y * Wj + s1.z * Whj;
+            sx += mi * (s1.y * Wrj + s1.z * Wrhj);
+        }
+        gx += sx * dx * inv_r;
+        gy += sx * dy * inv_r;
+        gz += sx * dz * inv_r;
+    };
+    auto sweep = [&](int ns) { pair_loop(m, ns, js, S, test, body); };
     int flushes = 0;
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJC, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    if (act) {
+    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
+    gm = stream_sum(gm, T_i); gh = stream_sum(gh, T_i);
+    if (lead) {
         J.arr(AJ_GX)[i] += gx;
         J.arr(AJ_GX + 1)[i] += gy;
         J.arr(AJ_GX + 2)[i] += gz;
@@ -269,8 +285,10 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const T h = a.hs[i];
@@ -284,32 +302,36 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     AdjPtrs<T> J{a.out, a.n};
     const T lhi = a.aux4[i].x;  // lambda_i h_i^3
     T gx = 0, gy = 0, gz = 0;
-    auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> s0 = m.s[0][k];
-            const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            const bool own = r2 < H2, rev = act && r2 < s0.w;
-            if ((!own && !rev) || !(r2 > (T)0)) continue;
-            const V4<T> s1 = m.s[1][k];  // (lambda_j h_j^3, 1/H_j)
-            const T inv_r = fast_rsqrt(r2);
-            const T r = r2 * inv_r;
-            T c = 0;
-            if (own) c += lhi * cn * iH4 * m4_dw(r * invH);
-            if (rev) {
-                const T ihj = s1.y;
-                c += s1.x * cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj);
-            }
-            gx -= c * dx * inv_r;
-            gy -= c * dy * inv_r;
-            gz -= c * dz * inv_r;
-        }
+    auto test = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
+        return (r2 < H2 || (act && r2 < s0.w)) && r2 > (T)0;
     };
+    auto body = [&](int k) {
+        const V4<T> s0 = m.s[0][k];
+        const T dx = pi.x - s0.x, dy = pi.y - s0.y, dz = pi.z - s0.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const bool own = r2 < H2, rev = act && r2 < s0.w;
+        const V4<T> s1 = m.s[1][k];  // (lambda_j h_j^3, 1/H_j)
+        const T inv_r = fast_rsqrt(r2);
+        const T r = r2 * inv_r;
+        T c = 0;
+        if (own) c += lhi * cn * iH4 * m4_dw(r * invH);
+        if (rev) {
+            const T ihj = s1.y;
+            c += s1.x * cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj);
+        }
+        gx -= c * dx * inv_r;
+        gy -= c * dy * inv_r;
+        gz -= c * dz * inv_r;
+    };
+    auto sweep = [&](int ns) { pair_loop(m, ns, js, S, test, body); };
     int flushes = 0;
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    if (act) {
+    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
+    if (lead) {
         J.arr(AJ_GX)[i] += gx;
         J.arr(AJ_GX + 1)[i] += gy;
         J.arr(AJ_GX + 2)[i] += gz;

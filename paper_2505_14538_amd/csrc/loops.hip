@@ -31,8 +31,10 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     if (tl.count <= 0) return;
     if (a.fixup && a.tflag[t] == 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -63,30 +65,33 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     T H = eps * h;
     T H2 = act ? mul_unfused(H, H) : (T)-1;
     T invH = (T)1 / H;
+    auto test = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        return dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+    };
+    auto body = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const V4<T> vj = m.s[1][k];
+        const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
+        const T q = r2 * inv_r * invH;
+        T w, s1, gq;
+        m4_terms(q, H * inv_r, w, s1, gq);
+        S0 += w;
+        S1 += s1;
+        Sr += sj.w * w;
+        Sdr += sj.w * s1;
+        const T ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+        const T mg = sj.w * gq;
+        Dv += mg * (ux * dx + uy * dy + uz * dz);
+        Cx += mg * (uy * dz - uz * dy);
+        Cy += mg * (uz * dx - ux * dz);
+        Cz += mg * (ux * dy - uy * dx);
+        ++cnt;
+    };
     auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> sj = m.s[0][k];
-            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            if (r2 < H2) {
-                const V4<T> vj = m.s[1][k];
-                const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
-                const T q = r2 * inv_r * invH;
-                T w, s1, gq;
-                m4_terms(q, H * inv_r, w, s1, gq);
-                S0 += w;
-                S1 += s1;
-                Sr += sj.w * w;
-                Sdr += sj.w * s1;
-                const T ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-                const T mg = sj.w * gq;
-                Dv += mg * (ux * dx + uy * dy + uz * dz);
-                Cx += mg * (uy * dz - uz * dy);
-                Cy += mg * (uz * dx - ux * dz);
-                Cz += mg * (ux * dy - uy * dx);
-                ++cnt;
-            }
-        }
+        pair_loop(m, ns, js, S, test, body);
         tested += (unsigned long long)ns;
     };
     auto zero = [&]() {
@@ -100,12 +105,13 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const bool cached = flushes == 0;
     for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
         ++iters;
+        const T S0r = stream_sum(S0, T_i), S1r = stream_sum(S1, T_i);
         if (!conv && !pend) {
-            const T G = S0;
+            const T G = S0r;
             if (fabs(G - Tt) <= a.h_tol * Tt) {
                 conv = true;
             } else {
-                const T dG = ((T)3 * S0 - S1) / h;
+                const T dG = ((T)3 * S0r - S1r) / h;
                 if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
                 T hn = h - (G - Tt) / dG;
                 const bool ok = dG > (T)0 && hn > lo_h && hn < hi_h;
@@ -135,11 +141,20 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
             sweep(ns);
         }
     }
+    S0 = stream_sum(S0, T_i);
+    S1 = stream_sum(S1, T_i);
+    Sr = stream_sum(Sr, T_i);
+    Sdr = stream_sum(Sdr, T_i);
+    Dv = stream_sum(Dv, T_i);
+    Cx = stream_sum(Cx, T_i);
+    Cy = stream_sum(Cy, T_i);
+    Cz = stream_sum(Cz, T_i);
+    cnt = stream_sum(cnt, T_i);
     const bool last = a.fixup == 2;
     if (pend && last) { failed = true; pend = false; }
     if (!conv && !pend && act) failed = true;
     // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
-    if (act) {
+    if (lead) {
         const T Hh = eps * h;
         const T iH = (T)1 / Hh;
         const T k3 = cnorm * iH * iH * iH;
@@ -163,9 +178,9 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
         a.hs[i] = pend ? want : h;
     }
     const unsigned long long pmask = ballot(pend);
-    const unsigned long long fmask = ballot(failed);
+    const unsigned long long fmask = ballot(failed && js == 0);
     const T wmax = wave_max(pend ? want : (T)0);
-    const unsigned long long ins = (unsigned long long)wave_sum(act ? cnt : 0);
+    const unsigned long long ins = (unsigned long long)wave_sum(lead ? cnt : 0);
     if (lane == 0) {
         if (pmask) {
             T Rn = eps * wmax * (T)1.125;
@@ -194,8 +209,10 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -211,37 +228,44 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     T vsig = (T)2 * ci, lap = 0;
     unsigned long long tested = 0;
     int inside = 0;
+    auto test = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
+        return r2 < H2 && r2 > (T)0;
+    };
+    auto body = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const V4<T> vj = m.s[1][k];
+        const T uj = m.s[2][k].x;
+        const T inv_r = fast_rsqrt(r2);
+        const T q = r2 * inv_r * invH;
+        const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+        const T mu = vr < (T)0 ? vr * inv_r : (T)0;
+        const T s = ci + vj.w - a.beta * mu;
+        vsig = s > vsig ? s : vsig;
+        const T t1 = (T)1 - q;
+        const T gq = q < (T)0.5 ? (T)18 * q - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
+        lap += sj.w * (ui - uj) * gq;
+        ++inside;
+    };
     auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> sj = m.s[0][k];
-            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            if (r2 < H2 && r2 > (T)0) {
-                const V4<T> vj = m.s[1][k];
-                const T uj = m.s[2][k].x;
-                const T inv_r = fast_rsqrt(r2);
-                const T q = r2 * inv_r * invH;
-                const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
-                const T mu = vr < (T)0 ? vr * inv_r : (T)0;
-                const T s = ci + vj.w - a.beta * mu;
-                vsig = s > vsig ? s : vsig;
-                const T t1 = (T)1 - q;
-                const T gq = q < (T)0.5 ? (T)18 * q - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
-                lap += sj.w * (ui - uj) * gq;
-                ++inside;
-            }
-        }
+        pair_loop(m, ns, js, S, test, body);
         tested += (unsigned long long)ns;
     };
     int flushes = 0;
     const int ns = stage_tile<L_GRAD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    if (act) {
+    vsig = stream_max(vsig, T_i);
+    lap = stream_sum(lap, T_i);
+    inside = stream_sum(inside, T_i);
+    if (lead) {
         const T k5 = (T)(8.0 / PI_D) * invH * invH * invH * invH * invH;
         a.out[0 * a.n + i] = vsig;
         a.out[1 * a.n + i] = (T)2 * k5 * lap;
     }
-    const unsigned long long ins = (unsigned long long)wave_sum(act ? inside : 0);
+    const unsigned long long ins = (unsigned long long)wave_sum(lead ? inside : 0);
     if (lane == 0) {
         atomicAdd(&a.cnt->pairs_tested[1], tested * (unsigned long long)tl.count);
         atomicAdd(&a.cnt->pairs_inside[1], ins);
@@ -255,8 +279,10 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const bool act = lane < tl.count;
-    const int i = tl.begin + (act ? lane : 0);
+    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const bool act = li < tl.count;
+    const bool lead = act && js == 0;  // writes the results of its i-particle
+    const int i = tl.begin + (act ? li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -276,55 +302,66 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     T ax = 0, ay = 0, az = 0, du = 0;
     int nint = 0;
     unsigned long long tested = 0;
-    auto sweep = [&](int ns) {
-        for (int k = 0; k < ns; ++k) {
-            const V4<T> sj = m.s[0][k];
-            const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
-            const T r2 = dist2_unfused(dx, dy, dz);
-            const T H2j = sj.w;
-            const int jj = as_int<T>(m.s[3][k].y);
-            if (act && r2 < max(H2, H2j) && jj != i) {
-                ++nint;
-                if (r2 > (T)0) {
-                    const V4<T> vj = m.s[1][k];
-                    const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
-                    const T rhoj = m.s[3][k].x;
-                    const T inv_r = fast_rsqrt(r2);
-                    const T r = r2 * inv_r;
-                    const T gi = r2 < H2 ? kgi * m4_dw(r * invH) : (T)0;
-                    const T ihj = cj.w;
-                    const T gj = r2 < H2j ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
-                    const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
-                    const T vdote = vr * inv_r;
-                    T nu = 0;
-                    if (visc) {
-                        const T mu = vdote < (T)0 ? vdote : (T)0;
-                        const T vs = ci + vj.w - beta * mu;
-                        nu = -alpha * mu * vs / (rhoi + rhoj);
-                    }
-                    const T mfg = cj.x * fi * gi + cj.z * gj;
-                    const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
-                    const T sr = sa * inv_r;
-                    ax -= sr * dx;
-                    ay -= sr * dy;
-                    az -= sr * dz;
-                    du += vdote * (cj.x * Ai * gi + (T)0.25 * nu * mfg);
-                }
-            }
+    // hits: every j (self included) with r < max(H_i, H_j); the self pair and
+    // coincident pairs (r = 0) add nothing to a and du/dt, so only r > 0 goes
+    // to the body, and nint = hits - 1 (the self pair is staged exactly once)
+    int hits = 0;
+    auto test = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
+        const bool in = act && r2 < max(H2, sj.w);
+        hits += in ? 1 : 0;
+        return in && r2 > (T)0;
+    };
+    auto body = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const T H2j = sj.w;
+        const V4<T> vj = m.s[1][k];
+        const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
+        const T rhoj = m.s[3][k].x;
+        const T inv_r = fast_rsqrt(r2);
+        const T r = r2 * inv_r;
+        const T gi = r2 < H2 ? kgi * m4_dw(r * invH) : (T)0;
+        const T ihj = cj.w;
+        const T gj = r2 < H2j ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
+        const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+        const T vdote = vr * inv_r;
+        T nu = 0;
+        if (visc) {
+            const T mu = vdote < (T)0 ? vdote : (T)0;
+            const T vs = ci + vj.w - beta * mu;
+            nu = -alpha * mu * vs / (rhoi + rhoj);
         }
+        const T mfg = cj.x * fi * gi + cj.z * gj;
+        const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
+        const T sr = sa * inv_r;
+        ax -= sr * dx;
+        ay -= sr * dy;
+        az -= sr * dz;
+        du += vdote * (cj.x * Ai * gi + (T)0.25 * nu * mfg);
+    };
+    auto sweep = [&](int ns) {
+        pair_loop(m, ns, js, S, test, body);
         tested += (unsigned long long)ns;
     };
     int flushes = 0;
     const int ns = stage_tile<L_FORCE, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    if (act) {
+    ax = stream_sum(ax, T_i);
+    ay = stream_sum(ay, T_i);
+    az = stream_sum(az, T_i);
+    du = stream_sum(du, T_i);
+    nint = stream_sum(hits, T_i) - 1;
+    if (lead) {
         a.out[0 * a.n + i] = ax;
         a.out[1 * a.n + i] = ay;
         a.out[2 * a.n + i] = az;
         a.out[3 * a.n + i] = du;
         a.iout[i] = nint;
     }
-    const unsigned long long ins = (unsigned long long)wave_sum(act ? nint : 0);
+    const unsigned long long ins = (unsigned long long)wave_sum(lead ? nint : 0);
     if (lane == 0) {
         atomicAdd(&a.cnt->pairs_tested[2], tested * (unsigned long long)tl.count);
         atomicAdd(&a.cnt->pairs_inside[2], ins);

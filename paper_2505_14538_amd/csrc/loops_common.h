@@ -9,10 +9,12 @@
 namespace swsph {
 
 constexpr int WPB = 4;  // wavefronts per workgroup
+constexpr int LC = 32;  // entries of a lane's hit list
 
 template <typename T, int CAP, int NV>
 struct WaveMem {
     V4<T> s[NV][CAP];          // staged j-particles
+    uint16_t lst[LC][WAVE];    // per-lane hit lists (staged indices), column per lane
     int32_t lbeg[WAVE];        // current batch of task-list leaves
     int32_t lpre[WAVE + 1];
     int32_t lshift[WAVE];
@@ -45,7 +47,55 @@ struct KArgs {
     int32_t h_max_iter;
     uint32_t flags;
     int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
+    int32_t tile;              // i-particles per tile (16, 32 or 64): lanes = tile x streams
 };
+
+// Lane mapping of a tile body: lane = i-slot + tile * stream.  Each of the
+// 64/tile streams of an i-particle walks every (64/tile)-th staged
+// j-particle; the partial sums of the streams are combined with xor
+// shuffles (lanes l and l ^ m share their i-slot when m is a multiple of
+// the tile size).
+template <typename V> __device__ __forceinline__ V stream_sum(V v, int tile) {
+    for (int m = tile; m < WAVE; m <<= 1) v += shfl_xor(v, m);
+    return v;
+}
+template <typename V> __device__ __forceinline__ V stream_max(V v, int tile) {
+    for (int m = tile; m < WAVE; m <<= 1) {
+        const V o = shfl_xor(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Pair loop over the staged j-particles with per-lane compaction.  Lane
+// (i-slot, stream js) runs the distance test over the staged indices
+// js, js + S, ...; the hits go, in index order, to the lane's own list in
+// LDS, and whenever some list is full (and at the end) every lane runs the
+// pair body over its list with the wavefront in step.  The body thus runs
+// with nearly all lanes busy instead of under the divergence of the test
+// (only ~1 in 5 tested pairs lies inside the support), and each lane still
+// accumulates its pairs in staged order, so results do not depend on LC.
+template <class WM, class Test, class Body>
+__device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& test,
+                                          Body&& body) {
+    const int lane = lane_id();
+    int c = 0;
+    auto drain = [&]() {
+        for (int e = 0; ballot(e < c) != 0ull; ++e) {
+            if (e < c) body((int)m.lst[e][lane]);
+        }
+        c = 0;
+    };
+    for (int k0 = 0; k0 < ns; k0 += S) {
+        const int k = k0 + js;
+        if (k < ns && test(k)) {
+            m.lst[c][lane] = (uint16_t)k;
+            ++c;
+        }
+        if (ballot(c == LC) != 0ull) drain();
+    }
+    drain();
+}
 
 // loop kinds: forward loops and the three pair passes of the adjoint
 enum { L_DENS = 0, L_GRAD = 1, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
@@ -238,6 +288,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.h_max_iter = sc.h_max_iter;
     a.flags = sc.flags;
     a.fixup = 0;
+    a.tile = b.tile;
     return a;
 }
 
