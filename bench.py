@@ -88,6 +88,7 @@ def run(args):
     for _ in range(args.warmup):
         step(plan)
     torch.cuda.synchronize()
+    log("warm-up done")
     plan.reset_timers()
     torch.cuda.synchronize()
     ev0.record()
@@ -103,20 +104,28 @@ def run(args):
     nngb = d["nngb"].to(torch.int64).sum().item()
     nint = f["nint"].to(torch.int64).sum().item()
     P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
-    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"]) / (args.steps + args.warmup)
+    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"])   # counters cover the last step
     value = (P_d + P_f) / t_step
     flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
     frac_peak = flops / t_step / PEAK_FP32
     log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
 
     # per-task launch baseline (same tile bodies, one launch per task)
+    log("per-task launch step (%d tasks per loop)" % st["n_tiles"])
     pt = S.Plan(flags=S.PER_TASK_LAUNCH)
-    step(pt)
     torch.cuda.synchronize()
     ev0.record()
-    step(pt)
+    pt.bin(dp)
+    dd = pt.density(dp)
+    torch.cuda.synchronize()
+    log("  density done")
+    pt.gradient(dp, dd)
+    torch.cuda.synchronize()
+    log("  gradient done")
+    pt.force(dp, dd)
     ev1.record()
     torch.cuda.synchronize()
+    log("  force done")
     t_pt = ev0.elapsed_time(ev1) / 1e3
     value_pt = (P_d + P_f) / t_pt
     log("per-task launch step %.1f ms" % (t_pt * 1e3))

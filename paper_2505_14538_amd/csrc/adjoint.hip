@@ -59,7 +59,7 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -201,7 +201,7 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -285,7 +285,7 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -351,20 +351,7 @@ __global__ void __launch_bounds__(WPB * WAVE) k_adj(KArgs<T> a, int mode) {
         else if (LK == L_ADJC) adjc_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t);
         else adjd_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t);
     };
-    if (mode == MODE_QUEUE) {
-        for (int guard = 0; guard <= a.n_tiles; ++guard) {
-            int t = 0;
-            if (lane_id() == 0) t = (int)atomicAdd(a.queue, 1ull);
-            t = uniform(__shfl(t, 0, WAVE));
-            if (t >= a.n_tiles || t < 0) break;
-            body(a.order[t]);
-        }
-    } else if (mode == MODE_FLAT) {
-        const int t = blockIdx.x * WPB + wave;
-        if (t < a.n_tiles) body(a.order[t]);
-    } else {
-        if (wave == 0 && a.task >= 0 && a.task < a.n_tiles) body(a.task);
-    }
+    for_each_task(a, mode, body);
 }
 
 template <int LK, typename T>

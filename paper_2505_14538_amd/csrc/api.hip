@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -39,8 +40,8 @@ uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 struct Geometry {
     int64_t n = 0;
     int32_t n_box = 0;
-    int32_t tile = 64;
-    int32_t n_tiles = 0;
+    int32_t tile = 32;
+    int64_t tile_cap = 0;   // most tiles the bin can make (one per particle)
     int64_t n_fine = 0, n_pyr = 0;
     int64_t leaf_cap = 0;
     int tsz = 4;
@@ -51,9 +52,10 @@ struct Geometry {
 constexpr int KMAX = 10;               // Morton key: 3 x 10 bits per box
 constexpr int64_t FINE_MAX = int64_t(1) << 29;
 
-// Task-list capacity: 384 cells per tile on average (a tile of a uniform
-// box needs ~30-120).  Overflow latches SWSPH_ST_CAPACITY.
-int64_t leaf_capacity(int32_t n_tiles) { return 384 * (int64_t)n_tiles + 4096; }
+// Task-list capacity: 48 cells per particle (cell tiles of <= 64 particles
+// need ~2-8 on clustered and uniform sets).  Overflow latches
+// SWSPH_ST_CAPACITY.
+int64_t leaf_capacity(int64_t n) { return 48 * n + 4096; }
 
 int choose_k(int64_t nb) {
     // finest grid with about one cell per particle or more (8^k <= 8 nb)
@@ -75,7 +77,6 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     G.tsz = tsz;
     G.boxes.assign(n_box, BoxInfo{});
     int64_t start = 0, fine = 0, pyr = 0, sum = 0;
-    int32_t toff = 0;
     for (int b = 0; b < n_box; ++b) {
         const int64_t nb = box_count ? box_count[b] : n;
         const double L = box_size[b];
@@ -88,20 +89,18 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
         bi.k = choose_k(nb);
         bi.fine_off = fine;
         bi.pyr_off = pyr;
-        bi.tile_off = toff;
-        bi.n_tiles = (int32_t)((nb + tile - 1) / tile);
         start += nb;
         sum += nb;
         fine += int64_t(1) << (3 * bi.k);
         pyr += pyr_level_off(bi.k + 1);
-        toff += bi.n_tiles;
         if (fine > FINE_MAX) return fail(SWSPH_E_ARG, "too many cells (boxes x grid)");
     }
     if (sum != n) return fail(SWSPH_E_ARG, "sum of box_count (%lld) != n (%lld)", (long long)sum,
                               (long long)n);
     G.n_fine = fine;
     G.n_pyr = pyr;
-    G.n_tiles = toff;
+    const int64_t toff = n > 0 ? n : 1;
+    G.tile_cap = toff;
     // layout
     Layout& l = G.lay;
     uint64_t o = 0;
@@ -116,12 +115,14 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.phase = take(sizeof(uint32_t) * 4 * n_box);
     l.keys = take(4 * N);
     l.slot = take(4 * N);
-    l.tmpidx = take(4 * N);
+    l.tmpidx = take(4 * (N + 1));
     l.perm = take(4 * N);
     l.rank = take(4 * N);
     l.fine_count = take(4 * (uint64_t)(fine + 1));
     l.cstart = take(4 * (uint64_t)(fine + 2));
-    l.scan_part = take(4 * (uint64_t)scan_partials_needed(fine + 1));
+    l.scan_part = take(4 * (uint64_t)std::max({scan_partials_needed(fine + 1),
+                                              scan_partials_needed(n + 1),
+                                              scan_partials_needed(order_table_size(n + 1))}));
     l.pos4 = take(4 * T * N);
     l.vel4 = take(4 * T * N);
     l.hs = take(T * N);
@@ -129,10 +130,12 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.hmaxpyr = take(4 * (uint64_t)pyr);
     l.tiles = take(sizeof(Tile) * (uint64_t)toff);
     l.order = take(4 * (uint64_t)toff);
+    l.ord_table = take(4 * (uint64_t)order_table_size(toff));
+    l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.leaf_cnt = take(4 * (uint64_t)(toff + 1));
     l.leaf_off = take(4 * (uint64_t)(toff + 2));
     l.leaf_part = take(4 * (uint64_t)scan_partials_needed(toff + 1));
-    G.leaf_cap = leaf_capacity(toff);
+    G.leaf_cap = leaf_capacity(n);
     l.leaves = take(8 * (uint64_t)G.leaf_cap);
     l.trad = take(4 * (uint64_t)toff);
     l.tflag = take(4 * (uint64_t)toff);
@@ -200,8 +203,8 @@ int check_config(const swsph_config* c) {
     if (!(c->h_tol > 0) || !(c->h_tol < 0.1)) return fail(SWSPH_E_ARG, "h_tol must be in (0, 0.1)");
     if (c->h_max_iter < 1 || c->h_max_iter > 1000) return fail(SWSPH_E_ARG, "h_max_iter in [1, 1000]");
     if (c->dtype != SWSPH_F32 && c->dtype != SWSPH_F64) return fail(SWSPH_E_ARG, "bad dtype");
-    if (c->tile != 0 && c->tile != 16 && c->tile != 32 && c->tile != 64)
-        return fail(SWSPH_E_ARG, "tile must be 0, 16, 32 or 64");
+    if (c->tile != 0 && c->tile != 8 && c->tile != 16 && c->tile != 32 && c->tile != 64)
+        return fail(SWSPH_E_ARG, "tile must be 0, 8, 16, 32 or 64");
     if (c->lds_cap != 0 && c->lds_cap != 128 && c->lds_cap != 256 && c->lds_cap != 512)
         return fail(SWSPH_E_ARG, "lds_cap must be 0, 128, 256 or 512");
     if (c->order != 0 && c->order != 1) return fail(SWSPH_E_ARG, "order must be 0 or 1");
@@ -239,6 +242,7 @@ Scheme scheme_of(const swsph_plan* pl) {
     s.h_max_iter = pl->cfg.h_max_iter;
     s.flags = pl->cfg.flags;
     s.leaf_max = pl->leaf_max;
+    s.order = pl->order;
     s.timer = pl->timer;
     return s;
 }
@@ -265,6 +269,8 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.hmaxpyr = (float*)(w + l.hmaxpyr);
     b.tiles = (Tile*)(w + l.tiles);
     b.order = (int32_t*)(w + l.order);
+    b.ord_table = (int32_t*)(w + l.ord_table);
+    b.ord_base = (int32_t*)(w + l.ord_base);
     b.leaf_cnt = (int32_t*)(w + l.leaf_cnt);
     b.leaf_off = (int32_t*)(w + l.leaf_off);
     b.leaf_part = (int32_t*)(w + l.leaf_part);
@@ -280,7 +286,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.adj = w + l.adj;
     b.n = pl->G.n;
     b.n_box = pl->G.n_box;
-    b.n_tiles = pl->G.n_tiles;
+    b.tile_cap = pl->G.tile_cap;
     b.tile = pl->G.tile;
     b.n_fine = pl->G.n_fine;
     b.n_pyr = pl->G.n_pyr;
@@ -335,7 +341,7 @@ void swsph_config_default(swsph_config* c) {
     c->flags = 0;
     c->tile = 0;
     c->lds_cap = 0;
-    c->order = 1;
+    c->order = 0;
     c->leaf_max = 0;
 }
 
@@ -347,7 +353,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     swsph_plan* pl = new (std::nothrow) swsph_plan();
     if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
     pl->cfg = *cfg;
-    pl->tile = cfg->tile ? cfg->tile : 64;
+    pl->tile = cfg->tile ? cfg->tile : 32;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 512;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
@@ -414,11 +420,11 @@ int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) 
     if (f64) {
         launch_gather<double>(p, b.boxtab, b.keys, b.cstart, b.perm, pl->cfg.eta, b.pos4, b.vel4,
                               b.hs, s);
-        launch_tiles<double>(G.n_tiles, G.tile, G.n_box, b.boxtab, b.pos4, b.hs, b.tiles, b.order, s);
+        launch_make_tiles<double>(b, s);
     } else {
         launch_gather<float>(p, b.boxtab, b.keys, b.cstart, b.perm, pl->cfg.eta, b.pos4, b.vel4,
                              b.hs, s);
-        launch_tiles<float>(G.n_tiles, G.tile, G.n_box, b.boxtab, b.pos4, b.hs, b.tiles, b.order, s);
+        launch_make_tiles<float>(b, s);
     }
     return hip_check(hipGetLastError(), "swsph_bin launch");
 }
@@ -550,7 +556,7 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
     if (r) return r;
     std::memset(out, 0, sizeof *out);
     out->status = (uint32_t)c.status;
-    out->n_tiles = (uint32_t)pl->G.n_tiles;
+    out->n_tiles = (uint32_t)c.n_tiles;
     for (int k = 0; k < 4; ++k) {
         out->pairs_tested[k] = c.pairs_tested[k];
         out->pairs_inside[k] = c.pairs_inside[k];

@@ -287,68 +287,121 @@ template void launch_gather<double>(const swsph_particles*, const BoxInfo*, cons
                                     hipStream_t);
 
 // ----------------------------------------------------------------- tiles
+// A tile (one task of the loops) is the coarsest cell of the box's cell
+// tree that holds at most `tile` particles; a finest cell holding more is
+// cut into runs of `tile`.  Tiles are cubes, so their bounding boxes are
+// compact and their task lists short even where the particle density
+// changes by orders of magnitude; they come out in Morton order per box.
+// Built in three passes: flag the first particle of every tile, scan the
+// flags (tile index), write the tiles.  The tile count stays on the device
+// (Counters::n_tiles); kernels over tiles loop up to it.
 
-// One wavefront per tile: its particle range, bounding box and largest h.
+// Sorted range [cbeg, cend) of the tile cell of binned particle s.
+__device__ __forceinline__ void tile_cell(int64_t s, const BoxInfo& bi, uint32_t mort,
+                                          const int32_t* __restrict__ cstart, int32_t tile,
+                                          int64_t& cbeg, int64_t& cend) {
+    const int k = bi.k;
+    for (int l = 0; l <= k; ++l) {
+        const int sh = 3 * (k - l);
+        const int64_t fb = bi.fine_off + (int64_t)((mort >> sh) << sh);
+        cbeg = cstart[fb];
+        cend = cstart[fb + (int64_t(1) << sh)];
+        if (cend - cbeg <= tile) return;
+    }
+}
+
+__global__ void k_tile_flags(int64_t n, int32_t n_box, const BoxInfo* __restrict__ boxtab,
+                             const uint32_t* __restrict__ keys, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ cstart, int32_t tile,
+                             int32_t* __restrict__ flag) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const BoxInfo bi = boxtab[box_of_sorted(s, n_box, boxtab)];
+    const uint32_t mort = keys[perm[s]] - (uint32_t)bi.fine_off;
+    int64_t cbeg = s, cend = s + 1;
+    tile_cell(s, bi, mort, cstart, tile, cbeg, cend);
+    flag[s] = ((s - cbeg) % tile) == 0 ? 1 : 0;
+}
+
+__global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict__ boxtab,
+                            const uint32_t* __restrict__ keys, const int32_t* __restrict__ perm,
+                            const int32_t* __restrict__ cstart, int32_t tile,
+                            const int32_t* __restrict__ flag, const int32_t* __restrict__ tidx,
+                            Tile* __restrict__ tiles, Counters* __restrict__ cnt) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (s == n - 1) cnt->n_tiles = (unsigned long long)tidx[n];
+    if (!flag[s]) return;
+    const int b = box_of_sorted(s, n_box, boxtab);
+    const BoxInfo bi = boxtab[b];
+    const uint32_t mort = keys[perm[s]] - (uint32_t)bi.fine_off;
+    int64_t cbeg = s, cend = s + 1;
+    tile_cell(s, bi, mort, cstart, tile, cbeg, cend);
+    Tile tl;
+    tl.begin = (int32_t)s;
+    tl.count = (int32_t)min((int64_t)tile, cend - s);
+    tl.box = b;
+    tl.flags = 0;
+    tiles[tidx[s]] = tl;
+}
+
+// One wavefront per tile (grid-stride over the device tile count): the
+// bounding box and largest h of its particles.
 template <typename T>
-__global__ void k_tiles(int32_t n_tiles, int32_t tile, int32_t n_box,
-                        const BoxInfo* __restrict__ boxtab, const V4<T>* __restrict__ pos4,
-                        const T* __restrict__ hs, Tile* __restrict__ tiles,
-                        int32_t* __restrict__ order) {
-    int t = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    if (t >= n_tiles) return;
+__global__ void k_tile_bounds(const V4<T>* __restrict__ pos4, const T* __restrict__ hs,
+                              Tile* __restrict__ tiles, int32_t* __restrict__ order,
+                              const Counters* __restrict__ cnt) {
+    const int64_t nt = (int64_t)cnt->n_tiles;
     const int lane = threadIdx.x & (WAVE - 1);
-    // box of tile t: last box with tile_off <= t
-    int lo = 0, hi = n_box - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (boxtab[mid].tile_off <= t) lo = mid; else hi = mid - 1;
-    }
-    const BoxInfo bi = boxtab[lo];
-    int j = t - bi.tile_off;
-    int64_t begin = bi.start + (int64_t)j * tile;
-    int64_t cnt = bi.count - (int64_t)j * tile;
-    if (cnt > tile) cnt = tile;
-    if (cnt < 0) cnt = 0;
-    bool act = lane < cnt;
-    float px = 0, py = 0, pz = 0, h = 0;
-    if (act) {
-        V4<T> a = pos4[begin + lane];
-        px = (float)a.x; py = (float)a.y; pz = (float)a.z;
-        h = (float)hs[begin + lane];
-    }
-    float lx = wave_min(act ? px : 3.0e38f), ly = wave_min(act ? py : 3.0e38f),
-          lz = wave_min(act ? pz : 3.0e38f);
-    float ux = wave_max(act ? px : -3.0e38f), uy = wave_max(act ? py : -3.0e38f),
-          uz = wave_max(act ? pz : -3.0e38f);
-    float hm = wave_max(act ? h : 0.0f);
-    if (lane == 0) {
-        Tile tl;
-        tl.begin = (int32_t)begin;
-        tl.count = (int32_t)cnt;
-        tl.box = lo;
-        tl.flags = 0;
-        tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;
-        tl.hi[0] = ux; tl.hi[1] = uy; tl.hi[2] = uz;
-        tl.hmax = hm;
-        tl.cost = (float)cnt;
-        tiles[t] = tl;
-        order[t] = t;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; t < nt;
+         t += nw) {
+        Tile tl = tiles[t];
+        const bool act = lane < tl.count;
+        float px = 0, py = 0, pz = 0, h = 0;
+        if (act) {
+            const V4<T> a = pos4[tl.begin + lane];
+            px = (float)a.x; py = (float)a.y; pz = (float)a.z;
+            h = (float)hs[tl.begin + lane];
+        }
+        const float lx = wave_min(act ? px : 3.0e38f), ly = wave_min(act ? py : 3.0e38f),
+                    lz = wave_min(act ? pz : 3.0e38f);
+        const float ux = wave_max(act ? px : -3.0e38f), uy = wave_max(act ? py : -3.0e38f),
+                    uz = wave_max(act ? pz : -3.0e38f);
+        const float hm = wave_max(act ? h : 0.0f);
+        if (lane == 0) {
+            tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;
+            tl.hi[0] = ux; tl.hi[1] = uy; tl.hi[2] = uz;
+            tl.hmax = hm;
+            tl.cost = (float)tl.count;
+            tiles[t] = tl;
+            order[t] = (int32_t)t;
+        }
     }
 }
 
-template <typename T>
-void launch_tiles(int32_t n_tiles, int32_t tile, int32_t n_box, const BoxInfo* boxtab,
-                  const void* pos4, const void* hs, Tile* tiles, int32_t* order, hipStream_t s) {
-    if (n_tiles <= 0) return;
-    const int wpb = 4;
-    hipLaunchKernelGGL(k_tiles<T>, dim3((unsigned)((n_tiles + wpb - 1) / wpb)), dim3(wpb * WAVE),
-                       0, s, n_tiles, tile, n_box, boxtab, (const V4<T>*)pos4, (const T*)hs, tiles,
-                       order);
+// Blocks for a grid-stride launch of one wavefront per item.
+unsigned wave_grid(int64_t items, int wpb) {
+    int64_t b = (items + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (b > cap) b = cap;
+    return (unsigned)(b > 0 ? b : 1);
 }
-template void launch_tiles<float>(int32_t, int32_t, int32_t, const BoxInfo*, const void*,
-                                  const void*, Tile*, int32_t*, hipStream_t);
-template void launch_tiles<double>(int32_t, int32_t, int32_t, const BoxInfo*, const void*,
-                                   const void*, Tile*, int32_t*, hipStream_t);
+
+template <typename T>
+void launch_make_tiles(const BinPtrs& b, hipStream_t s) {
+    if (b.n <= 0) return;
+    const unsigned g = (unsigned)((b.n + 255) / 256);
+    hipLaunchKernelGGL(k_tile_flags, dim3(g), dim3(256), 0, s, b.n, b.n_box, b.boxtab, b.keys,
+                       b.perm, b.cstart, b.tile, b.slot);
+    launch_exclusive_scan(b.slot, b.n, b.scan_part, b.tmpidx, s);
+    hipLaunchKernelGGL(k_tile_make, dim3(g), dim3(256), 0, s, b.n, b.n_box, b.boxtab, b.keys,
+                       b.perm, b.cstart, b.tile, b.slot, b.tmpidx, b.tiles, b.cnt);
+    hipLaunchKernelGGL(k_tile_bounds<T>, dim3(wave_grid(b.tile_cap, 4)), dim3(4 * WAVE), 0, s,
+                       (const V4<T>*)b.pos4, (const T*)b.hs, b.tiles, b.order, b.cnt);
+}
+template void launch_make_tiles<float>(const BinPtrs&, hipStream_t);
+template void launch_make_tiles<double>(const BinPtrs&, hipStream_t);
 
 // ------------------------------------------------------ unsort of outputs
 

@@ -17,6 +17,7 @@ struct Scheme {
     int32_t h_max_iter;
     uint32_t flags;
     int32_t leaf_max;
+    int32_t order;  // 0: tiles by decreasing cost, 1: in Morton order
     Timer* timer;   // nullable
 };
 
@@ -32,6 +33,7 @@ struct BinPtrs {
     float* hmaxpyr;
     Tile* tiles;
     int32_t* order;
+    int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *leaf_cnt, *leaf_off, *leaf_part;
     int2* leaves;
     int64_t leaf_cap;
@@ -40,7 +42,9 @@ struct BinPtrs {
     void *d_out, *g_out, *f_out, *adj;
     int32_t *d_int, *f_int;
     int64_t n;
-    int32_t n_box, n_tiles, tile;
+    int32_t n_box;
+    int32_t tile;      // most particles per tile
+    int64_t tile_cap;  // most tiles (the device holds the count: cnt->n_tiles)
     int64_t n_fine, n_pyr;
 };
 
@@ -62,8 +66,8 @@ void launch_gather(const swsph_particles* p, const BoxInfo* boxtab, const uint32
                    const int32_t* cstart, const int32_t* perm, double eta, void* pos4,
                    void* vel4, void* hs, hipStream_t s);
 template <typename T>
-void launch_tiles(int32_t n_tiles, int32_t tile, int32_t n_box, const BoxInfo* boxtab,
-                  const void* pos4, const void* hs, Tile* tiles, int32_t* order, hipStream_t s);
+void launch_make_tiles(const BinPtrs& b, hipStream_t s);
+unsigned wave_grid(int64_t items, int wpb);
 template <typename T>
 void launch_unsort(int64_t n, const int32_t* rank, const void* in, void* out, hipStream_t s);
 template <typename T>
@@ -72,6 +76,7 @@ void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, 
 // tasks.hip: mode 0 density, 1 gradient, 2 force; fixup: only flagged tiles
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s);
+int64_t order_table_size(int64_t tile_cap);
 
 // loops.hip
 template <typename T>

@@ -31,7 +31,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     if (tl.count <= 0) return;
     if (a.fixup && a.tflag[t] == 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -50,6 +50,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const T tiny = (sizeof(T) == 4) ? (T)2.4e-7 : (T)4.5e-16;
     const T R = (T)a.trad[t];
     const T hstage = R / eps;
+    const T hedge = hstage * ((T)1 - (T)8 * tiny);  // largest h whose support is staged
     (void)L;
 
     T lo_h = 0, hi_h = hstage;
@@ -116,9 +117,11 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
                 T hn = h - (G - Tt) / dG;
                 const bool ok = dG > (T)0 && hn > lo_h && hn < hi_h;
                 if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
-                if (!has_upper && hn >= hstage) {
-                    // the root lies beyond the staged radius: fix-up pass
-                    if (R >= Rcap) { failed = true; conv = true; }
+                if (!has_upper && hn >= hedge) {
+                    // the step leaves the staged set: first try its edge; if
+                    // the root lies beyond, the tile gets a fix-up pass
+                    if (h < hedge) h = hedge;
+                    else if (R >= Rcap) { failed = true; conv = true; }
                     else { pend = true; want = hn; }
                 } else if (fabs(hn - h) <= tiny * h) {
                     conv = true;
@@ -209,7 +212,7 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -279,7 +282,7 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     const Tile tl = a.tiles[t];
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = a.tile, li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
+    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
     const bool act = li < tl.count;
     const bool lead = act && js == 0;  // writes the results of its i-particle
     const int i = tl.begin + (act ? li : 0);
@@ -383,22 +386,7 @@ __global__ void __launch_bounds__(WPB * WAVE) k_loop(KArgs<T> a, int mode) {
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
     const int wave = threadIdx.x / WAVE;
     char* wm = smem + wave * WMS;
-    if (mode == MODE_QUEUE) {
-        // every wavefront pops tasks until the queue is drained; the loop
-        // runs at most n_tiles + 1 times per wavefront
-        for (int guard = 0; guard <= a.n_tiles; ++guard) {
-            int t = 0;
-            if (lane_id() == 0) t = (int)atomicAdd(a.queue, 1ull);
-            t = uniform(__shfl(t, 0, WAVE));
-            if (t >= a.n_tiles || t < 0) break;
-            run_tile<LK, T, CAP>(wm, a, a.order[t]);
-        }
-    } else if (mode == MODE_FLAT) {
-        const int t = blockIdx.x * WPB + wave;
-        if (t < a.n_tiles) run_tile<LK, T, CAP>(wm, a, a.order[t]);
-    } else {
-        if (wave == 0 && a.task >= 0 && a.task < a.n_tiles) run_tile<LK, T, CAP>(wm, a, a.task);
-    }
+    for_each_task(a, mode, [&](int t) { run_tile<LK, T, CAP>(wm, a, t); });
 }
 
 int device_cu_count() {
@@ -511,17 +499,6 @@ template void launch_prep_dens<double>(const BinPtrs&, const Scheme&, const swsp
 // Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
 // of every box: fine cells by atomic max over particles, then each fine cell
 // pushes its value up while it raises the parent.
-// Box of the binned particle s: boxes occupy consecutive ranges.
-__device__ __forceinline__ int box_of_sorted(int64_t s, int32_t n_box,
-                                             const BoxInfo* __restrict__ boxtab) {
-    int lo = 0, hi = n_box - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (boxtab[mid].start <= s) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <typename T>
 __global__ void k_hmax_fine(int64_t n, const int32_t* __restrict__ perm,
                             const uint32_t* __restrict__ keys, int32_t n_box,

@@ -25,7 +25,7 @@ struct KArgs {
     const BoxInfo* boxtab;
     const Tile* tiles;
     const int32_t* order;
-    int32_t n_tiles;
+    int64_t tile_cap;          // bound of the device tile count (cnt->n_tiles)
     int32_t task;              // per-task launch: the task to run
     const int32_t* leaf_cnt;
     const int32_t* leaf_off;
@@ -47,8 +47,15 @@ struct KArgs {
     int32_t h_max_iter;
     uint32_t flags;
     int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
-    int32_t tile;              // i-particles per tile (16, 32 or 64): lanes = tile x streams
 };
+
+// Lane mapping of a tile of c particles: i-slots = the power of two >= c,
+// streams = 64 / i-slots.
+__device__ __forceinline__ int islots_of(int c) {
+    int t = 1;
+    while (t < c && t < WAVE) t <<= 1;
+    return t;
+}
 
 // Lane mapping of a tile body: lane = i-slot + tile * stream.  Each of the
 // 64/tile streams of an i-particle walks every (64/tile)-th staged
@@ -261,7 +268,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
     a.order = b.order;
-    a.n_tiles = b.n_tiles;
+    a.tile_cap = b.tile_cap;
     a.task = 0;
     a.leaf_cnt = b.leaf_cnt;
     a.leaf_off = b.leaf_off;
@@ -288,13 +295,36 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.h_max_iter = sc.h_max_iter;
     a.flags = sc.flags;
     a.fixup = 0;
-    a.tile = b.tile;
     return a;
 }
 
+// Task dispatch inside a loop kernel: the persistent queue (every wavefront
+// pops tile tasks until the queue is drained; at most tile_cap + 1 pops),
+// the static round-robin schedule, or the one task of a per-task launch.
+template <typename T, class Run>
+__device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&& run) {
+    const int wave = threadIdx.x / WAVE;
+    const int64_t nt = (int64_t)a.cnt->n_tiles;
+    if (mode == MODE_QUEUE) {
+        for (int64_t guard = 0; guard <= a.tile_cap; ++guard) {
+            int t = 0;
+            if (lane_id() == 0) t = (int)atomicAdd(a.queue, 1ull);
+            t = uniform(__shfl(t, 0, WAVE));
+            if (t < 0 || t >= nt) break;
+            run(a.order[t]);
+        }
+    } else if (mode == MODE_FLAT) {
+        const int64_t nw = (int64_t)gridDim.x * WPB;
+        for (int64_t t = blockIdx.x * (int64_t)WPB + wave; t < nt; t += nw) run(a.order[t]);
+    } else {
+        if (wave == 0 && a.task >= 0 && a.task < nt) run(a.task);
+    }
+}
+
 // Launch a loop kernel (k(args, mode)) in one of the three modes: the
-// persistent queue (grid = resident workgroups), flat (a wavefront per task)
-// or one launch per task.
+// persistent queue (grid = resident workgroups, tasks popped from a device
+// counter), flat (the same grid, tasks dealt round-robin: a static schedule)
+// or one launch per task (reads the tile count back: synchronises).
 template <int LK, typename T, int CAP>
 int launch_with(void (*kern)(KArgs<T>, int), KArgs<T> a, int mode, int queue_slot,
                 hipStream_t s) {
@@ -307,25 +337,27 @@ int launch_with(void (*kern)(KArgs<T>, int), KArgs<T> a, int mode, int queue_slo
             return -1;
         attr_set = true;
     }
-    if (a.n_tiles <= 0) return 0;
+    if (a.tile_cap <= 0) return 0;
     a.queue = &a.cnt->queue[queue_slot];
-    if (mode == MODE_QUEUE) {
-        launch_fill_u32(a.queue, 2, 0u, s);
+    if (mode == MODE_QUEUE || mode == MODE_FLAT) {
+        if (mode == MODE_QUEUE) launch_fill_u32(a.queue, 2, 0u, s);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WPB * WAVE,
                                                          shm) != hipSuccess)
             per_cu = 1;
         if (per_cu < 1) per_cu = 1;
         int64_t blocks = (int64_t)per_cu * device_cu_count();
-        const int64_t need = (a.n_tiles + WPB - 1) / WPB;
+        const int64_t need = (a.tile_cap + WPB - 1) / WPB;
         if (blocks > need) blocks = need;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, a, (int)MODE_QUEUE);
-    } else if (mode == MODE_FLAT) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)((a.n_tiles + WPB - 1) / WPB)), dim3(WPB * WAVE),
-                           shm, s, a, (int)MODE_FLAT);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, a, mode);
     } else {
-        for (int t = 0; t < a.n_tiles; ++t) {
-            a.task = t;
+        unsigned long long nt = 0;
+        if (hipMemcpyAsync(&nt, &a.cnt->n_tiles, sizeof nt, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return -1;
+        for (int64_t t = 0; t < (int64_t)nt; ++t) {
+            a.task = (int32_t)t;
             hipLaunchKernelGGL(kern, dim3(1), dim3(WAVE), WMS, s, a, (int)MODE_PER_TASK);
         }
     }

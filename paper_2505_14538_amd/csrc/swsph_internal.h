@@ -28,15 +28,15 @@ struct BoxInfo {
     int64_t fine_off;   // offset of the box's cells in the fine cell table
     int64_t pyr_off;    // offset of the box's level-0 entry in the H-max pyramid
     int32_t k;          // fine level: 2^k cells per dimension
-    int32_t tile_off;   // first tile of the box
-    int32_t n_tiles;    // tiles of the box
-    int32_t pad;
+    int32_t pad[3];
 };
 
-// One i-tile task: up to `tile` consecutive binned particles of one box.
+// One i-tile task: the particles of one cubic cell of the box's cell tree
+// (the coarsest cell holding at most `tile` particles), or a run of at most
+// `tile` particles of an overfull finest cell.  Consecutive binned particles.
 struct Tile {
     int32_t begin;      // first binned particle
-    int32_t count;      // particles (<= tile size)
+    int32_t count;      // particles (1 .. tile size)
     int32_t box;
     int32_t flags;
     float lo[3], hi[3]; // bounding box of the tile's particles
@@ -56,7 +56,8 @@ struct Counters {
     unsigned long long restages;
     unsigned long long queue[8];       // task-queue heads of the loops
     unsigned long long leaf_need;      // leaves requested by the last task build
-    unsigned long long reserved[9];
+    unsigned long long n_tiles;        // tiles made by the last bin
+    unsigned long long reserved[8];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };
@@ -64,10 +65,10 @@ enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD =
 // Byte offsets of every workspace region (computed on the host).
 struct Layout {
     uint64_t counters, boxtab, phase;      // phase: per-box done counters (2 per box)
-    uint64_t keys, slot, tmpidx, perm, rank;
+    uint64_t keys, slot, tmpidx, perm, rank;  // slot/tmpidx: reused for the tile scan
     uint64_t fine_count, cstart, scan_part;
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
-    uint64_t tiles, order;
+    uint64_t tiles, order, ord_table, ord_base;
     // task lists (CSR of cells per tile) and density fix-up state
     uint64_t leaf_cnt, leaf_off, leaf_part, leaves, trad, tflag;
     // sorted-order results
@@ -193,6 +194,17 @@ __host__ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
 // Offset of level l inside one box's pyramid (levels 0..k, 8^l cells each).
 __host__ __device__ __forceinline__ int64_t pyr_level_off(int l) {
     return ((int64_t(1) << (3 * l)) - 1) / 7;
+}
+
+// Box of the binned particle s: boxes occupy consecutive ranges.
+__device__ __forceinline__ int box_of_sorted(int64_t s, int32_t n_box,
+                                             const BoxInfo* __restrict__ boxtab) {
+    int lo = 0, hi = n_box - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxtab[mid].start <= s) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 }  // namespace swsph

@@ -18,7 +18,7 @@ template <typename T>
 struct TArgs {
     const BoxInfo* boxtab;
     Tile* tiles;
-    int32_t n_tiles;
+    int64_t tile_cap;
     const int32_t* cstart;
     const float* hpyr;
     const T* hs;
@@ -34,25 +34,12 @@ struct TArgs {
     int32_t leaf_max;
 };
 
-// MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
-// 2 force (eps*hmax, and cells whose own support reaches the tile).
+// Task list of tile t (count pass: size, radius and cost; fill pass: the
+// leaves).  Wavefront-uniform.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int pass, int fixup) {
-    __shared__ SearchMem smem_search[TASK_WPB];
-    const int wave = threadIdx.x / WAVE;
-    const int t = blockIdx.x * TASK_WPB + wave;
-    if (t >= a.n_tiles) return;
-    SearchMem& m = smem_search[wave];
+__device__ void task_one(const TArgs<T>& a, SearchMem& m, const Tile& tl, int64_t t, int pass,
+                         int fixup) {
     const int lane = lane_id();
-    const Tile tl = a.tiles[t];
-    const bool skip = tl.count <= 0 || (fixup && a.tflag[t] == 0);
-    if (skip) {
-        if (pass == 0 && lane == 0) {
-            a.leaf_cnt[t] = 0;
-            if (!fixup) a.trad[t] = 0.f;
-        }
-        return;
-    }
     const BoxInfo bi = a.boxtab[tl.box];
     const float L = (float)bi.L;
     const float Rcap = 0.5f * L * (1.0f - 1e-6f);
@@ -112,6 +99,121 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int pass,
             latch(a.cnt, SWSPH_ST_CAPACITY);
         }
     }
+    wave_sync();
+}
+
+// MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
+// 2 force (eps*hmax, and cells whose own support reaches the tile).
+// One wavefront per tile, grid-stride over the device tile count; the count
+// pass also zeroes the counts of the unused tile slots (the scan runs over
+// all of them).
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int pass, int fixup) {
+    __shared__ SearchMem smem_search[TASK_WPB];
+    const int wave = threadIdx.x / WAVE;
+    SearchMem& m = smem_search[wave];
+    const int lane = lane_id();
+    const int64_t nt = (int64_t)a.cnt->n_tiles;
+    if (pass == 0) {
+        const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t t = nt + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.tile_cap;
+             t += nth)
+            a.leaf_cnt[t] = 0;
+    }
+    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
+    for (int64_t t = blockIdx.x * (int64_t)TASK_WPB + wave; t < nt; t += nw) {
+        const Tile tl = a.tiles[t];
+        const bool skip = tl.count <= 0 || (fixup && a.tflag[t] == 0);
+        if (skip) {
+            if (pass == 0 && lane == 0) {
+                a.leaf_cnt[t] = 0;
+                if (!fixup) a.trad[t] = 0.f;
+            }
+            continue;
+        }
+        task_one<T, MODE>(a, m, tl, t, pass, fixup);
+    }
+}
+
+// Queue order of the tiles by decreasing cost (longest task first), so the
+// persistent kernel does not end on a few large tasks.  A stable counting
+// sort on 32 logarithmic cost classes: blocks own contiguous runs of
+// ORD_T x ORD_I tiles and threads contiguous runs of ORD_I, so equal classes
+// keep tile order and the result is deterministic.  Three launches: per
+// block class histograms, a scan of the class-major table, the scatter.
+constexpr int ORD_T = 256, ORD_I = 8, ORD_B = 32;
+constexpr int ORD_CHUNK = ORD_T * ORD_I;
+
+__device__ __forceinline__ int cost_class(float c) {
+    int e = 0;
+    if (c >= 1.f) frexpf(c, &e);                      // c in [2^(e-1), 2^e)
+    return max(0, min(ORD_B - 1, ORD_B - 1 - e));     // large cost -> small class
+}
+
+// Per-thread class counts of the block's tiles, exclusive over the block's
+// threads (hist[c][k] = tiles of class c before thread k's run).
+__device__ __forceinline__ void block_class_counts(const Tile* __restrict__ tiles, int64_t nt,
+                                                   int32_t (&hist)[ORD_B][ORD_T],
+                                                   int32_t (&tot)[ORD_B], int64_t& lo,
+                                                   int64_t& hi) {
+    const int k = threadIdx.x;
+    lo = min(nt, (int64_t)blockIdx.x * ORD_CHUNK + (int64_t)k * ORD_I);
+    hi = min(nt, lo + ORD_I);
+    for (int c = 0; c < ORD_B; ++c) hist[c][k] = 0;
+    for (int64_t t = lo; t < hi; ++t) ++hist[cost_class(tiles[t].cost)][k];
+    __syncthreads();
+    if (k < ORD_B) {
+        int run = 0;
+        for (int j = 0; j < ORD_T; ++j) {
+            const int v = hist[k][j];
+            hist[k][j] = run;
+            run += v;
+        }
+        tot[k] = run;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(ORD_T) k_order_hist(const Tile* __restrict__ tiles,
+                                                      const Counters* __restrict__ cnt,
+                                                      int32_t nblk, int32_t* __restrict__ table) {
+    __shared__ int32_t hist[ORD_B][ORD_T];
+    __shared__ int32_t tot[ORD_B];
+    const int64_t nt = (int64_t)cnt->n_tiles;
+    int64_t lo, hi;
+    block_class_counts(tiles, nt, hist, tot, lo, hi);
+    if (threadIdx.x < ORD_B) table[(int64_t)threadIdx.x * nblk + blockIdx.x] = tot[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(ORD_T) k_order_scatter(const Tile* __restrict__ tiles,
+                                                         const Counters* __restrict__ cnt,
+                                                         int32_t nblk,
+                                                         const int32_t* __restrict__ base,
+                                                         int32_t* __restrict__ order) {
+    __shared__ int32_t hist[ORD_B][ORD_T];
+    __shared__ int32_t tot[ORD_B];
+    const int64_t nt = (int64_t)cnt->n_tiles;
+    int64_t lo, hi;
+    block_class_counts(tiles, nt, hist, tot, lo, hi);
+    const int k = threadIdx.x;
+    for (int64_t t = lo; t < hi; ++t) {
+        const int c = cost_class(tiles[t].cost);
+        order[base[(int64_t)c * nblk + blockIdx.x] + hist[c][k]++] = (int32_t)t;
+    }
+}
+
+int64_t order_table_size(int64_t tile_cap) {
+    return (int64_t)ORD_B * ((tile_cap + ORD_CHUNK - 1) / ORD_CHUNK) + 1;
+}
+
+void launch_order(const BinPtrs& b, hipStream_t s) {
+    const int32_t nblk = (int32_t)((b.tile_cap + ORD_CHUNK - 1) / ORD_CHUNK);
+    const int64_t nent = (int64_t)ORD_B * nblk;
+    hipLaunchKernelGGL(k_order_hist, dim3(nblk), dim3(ORD_T), 0, s, (const Tile*)b.tiles,
+                       (const Counters*)b.cnt, nblk, b.ord_table);
+    launch_exclusive_scan(b.ord_table, nent, b.scan_part, b.ord_base, s);
+    hipLaunchKernelGGL(k_order_scatter, dim3(nblk), dim3(ORD_T), 0, s, (const Tile*)b.tiles,
+                       (const Counters*)b.cnt, nblk, (const int32_t*)b.ord_base, b.order);
 }
 
 template <typename T>
@@ -119,7 +221,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     TArgs<T> a;
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
-    a.n_tiles = b.n_tiles;
+    a.tile_cap = b.tile_cap;
     a.cstart = b.cstart;
     a.hpyr = b.hmaxpyr;
     a.hs = (const T*)b.hs;
@@ -138,18 +240,19 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
 
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s) {
-    if (b.n_tiles <= 0) return;
+    if (b.n <= 0) return;
     const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? 1.25 : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
-    const dim3 grid((unsigned)((b.n_tiles + TASK_WPB - 1) / TASK_WPB)), block(TASK_WPB * WAVE);
+    const dim3 grid(wave_grid(b.tile_cap, TASK_WPB)), block(TASK_WPB * WAVE);
     void (*kern)(TArgs<T>, int, int) =
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
     auto run = [&](int pass) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, a, pass, (int)fixup);
     };
     run(0);
-    launch_exclusive_scan(b.leaf_cnt, b.n_tiles, b.leaf_part, b.leaf_off, s);
+    launch_exclusive_scan(b.leaf_cnt, b.tile_cap, b.leaf_part, b.leaf_off, s);
     run(1);
+    if (!fixup && sc.order == 0) launch_order(b, s);
 }
 template void launch_tasks<float>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
 template void launch_tasks<double>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
