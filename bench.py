@@ -65,53 +65,12 @@ def cpu_baseline(parts):
                       "(%.1f s) + force on %d random particles (%.1f s)" % (parts.n, t_d, ns, t_f)}
 
 
-def run(args):
+def per_task_step(S, dp, n_tiles):
+    """One step with one kernel launch per tile task (the same tile bodies):
+    the per-task offload baseline."""
     import torch
-    from paper_2505_14538_amd import swsph as S
-    from paper_2505_14538_amd import workloads as W
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    log("generating clustered workload")
-    parts = W.clustered()
-    dp = S.to_device(parts)
-    plan = S.Plan(flags=S.TIMING)
+    log("per-task launch step (%d tasks per loop)" % n_tiles)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def step(pl):
-        pl.bin(dp)
-        d = pl.density(dp)
-        g = pl.gradient(dp, d)
-        f = pl.force(dp, d)
-        return d, g, f
-
-    for _ in range(args.warmup):
-        step(plan)
-    torch.cuda.synchronize()
-    log("warm-up done")
-    plan.reset_timers()
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        d, g, f = step(plan)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_step = ev0.elapsed_time(ev1) / 1e3 / args.steps
-    st = plan.stats()
-    if st["code"] != 0:
-        raise SystemExit("device status %s" % st)
-    kt = plan.kernel_times()   # ms per launch of the loop kernels (HIP events)
-    nngb = d["nngb"].to(torch.int64).sum().item()
-    nint = f["nint"].to(torch.int64).sum().item()
-    P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
-    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"])   # counters cover the last step
-    value = (P_d + P_f) / t_step
-    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
-    frac_peak = flops / t_step / PEAK_FP32
-    log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
-
-    # per-task launch baseline (same tile bodies, one launch per task)
-    log("per-task launch step (%d tasks per loop)" % st["n_tiles"])
     pt = S.Plan(flags=S.PER_TASK_LAUNCH)
     torch.cuda.synchronize()
     ev0.record()
@@ -126,15 +85,86 @@ def run(args):
     ev1.record()
     torch.cuda.synchronize()
     log("  force done")
-    t_pt = ev0.elapsed_time(ev1) / 1e3
-    value_pt = (P_d + P_f) / t_pt
-    log("per-task launch step %.1f ms" % (t_pt * 1e3))
+    return ev0.elapsed_time(ev1) / 1e3
 
-    # roofline of the dominant kernel (largest share of the step)
+
+def copy_probe(nbytes):
+    """A plain device copy of nbytes, five times: the reference for scaling
+    the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy probe: 5 copies of %d bytes" % nbytes)
+
+
+def run(args):
+    import torch
+    from paper_2505_14538_amd import swsph as S
+    from paper_2505_14538_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    log("generating clustered workload")
+    parts = W.clustered()
+    dp = S.to_device(parts)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # the batched path: the whole step captured in a HIP graph by the library
+    # (bin + three persistent loop launches), replayed each step
+    plan = S.Plan()
+    for _ in range(args.warmup):
+        d, g, f = plan.step(dp)
+    torch.cuda.synchronize()
+    log("warm-up done")
+    ev0.record()
+    for _ in range(args.steps):
+        d, g, f = plan.step(dp)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_step = ev0.elapsed_time(ev1) / 1e3 / args.steps
+    st = plan.stats()
+    if st["code"] != 0:
+        raise SystemExit("device status %s" % st)
+    nngb = d["nngb"].to(torch.int64).sum().item()
+    nint = f["nint"].to(torch.int64).sum().item()
+    P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
+    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"])   # counters cover the last step
+    value = (P_d + P_f) / t_step
+    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
+    frac_peak = flops / t_step / PEAK_FP32
+    log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
+
+    # per-launch duration of the loop kernels: the same step run eagerly with
+    # HIP events recorded by the library on this stream around every launch
+    tp = S.Plan(flags=S.TIMING)
+    tp.step(dp)
+    torch.cuda.synchronize()
+    tp.reset_timers()
+    for _ in range(args.steps):
+        tp.step(dp)
+    kt = tp.kernel_times()
+    log("kernel ms per launch: " + ", ".join("%s %.3f (%d)" % (k, v["ms"], v["launches"])
+                                             for k, v in kt.items()))
+
+    t_pt = value_pt = None
+    if not args.no_per_task:
+        t_pt = per_task_step(S, dp, st["n_tiles"])
+        value_pt = (P_d + P_f) / t_pt
+        log("per-task launch step %.1f ms" % (t_pt * 1e3))
+
+
+    # roofline of the dominant kernel (largest share of the step); the
+    # density kernel runs once plus its fix-up passes per step, so its
+    # algorithmic FLOPs per launch are the step's density FLOPs divided by
+    # the launches per step
     dom = max(kt, key=lambda k: kt[k]["ms"] * kt[k]["launches"])
     k_ms = kt[dom]["ms"]
+    per_step = kt[dom]["launches"] / args.steps
     per_launch_flops = {"density": P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON),
-                        "gradient": P_g * F_GRAD, "force": P_f * F_FORCE}[dom]
+                        "gradient": P_g * F_GRAD, "force": P_f * F_FORCE}[dom] / per_step
     achieved = per_launch_flops / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
@@ -161,8 +191,8 @@ def run(args):
                       (kt[k]["ms"] * 1e-3), "kernel_ms": kt[k]["ms"]} for k in kt},
         "frac_fp32_peak": frac_peak,
         "newton_sweeps_per_tile": sweeps,
-        "per_task_launch": {"value": value_pt, "ms_per_step": t_pt * 1e3,
-                            "batched_speedup": t_pt / t_step},
+        "per_task_launch": None if args.no_per_task else {
+            "value": value_pt, "ms_per_step": t_pt * 1e3, "batched_speedup": t_pt / t_step},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -177,10 +207,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-per-task", action="store_true",
+                    help="skip the per-task launch baseline (for profiler runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py runs on one GPU only: --gpus must be 1 (sharding the loops "
                          "over several GPUs is not implemented)")
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     run(args)
 
 

@@ -24,10 +24,11 @@
  * the paper's tests, Sec. 3.1).  Cells and tasks: the paper splits the box
  * into cubic cells and runs "self" (one cell) and "pair" (two neighbouring
  * cells) tasks (Sec. 2.2.2); here particles are binned on the GPU into a
- * hierarchy of cubic cells (Morton order, counting sort), grouped into
- * i-tiles, and each tile's task is the list of cells -- its own (self) and
- * neighbouring ones (pairs) -- found by a recursive cell search, in the
- * spirit of the paper's sub-task recursion down to cells of width ~H.
+ * hierarchy of cubic cells (Morton order, counting sort); every coarsest
+ * cell holding at most `tile` particles is an i-tile, and each tile's task
+ * is the list of cells -- its own (self) and neighbouring ones (pairs) --
+ * found by a recursive cell search, in the spirit of the paper's sub-task
+ * recursion down to cells of width ~H.
  *
  * ---------------------------------------------------------------------------
  * Conventions for every entry point
@@ -103,9 +104,9 @@ typedef struct swsph_config {
     int32_t h_max_iter;  /* Newton sweeps before SWSPH_ST_NEWTON is latched */
     int32_t dtype;       /* swsph_dtype of every particle array */
     uint32_t flags;      /* SWSPH_* flags above */
-    int32_t tile;        /* i-particles per task: 16, 32 or 64 (0: auto) */
-    int32_t lds_cap;     /* staged j-particles per wavefront: 128..1024 (0: auto) */
-    int32_t order;       /* task order: 0 cost-descending, 1 Morton (tile order) */
+    int32_t tile;        /* most i-particles per task: 8, 16, 32 or 64 (0: 32) */
+    int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 512) */
+    int32_t order;       /* task order: 0 cost-descending (default), 1 Morton */
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: auto) */
     int32_t reserved[5];
 } swsph_config;
@@ -228,11 +229,15 @@ int swsph_force_backward(swsph_plan* plan, const swsph_particles* p,
                          const swsph_density_out* d, const swsph_force_grad* g,
                          swsph_input_grad* gi, void* ws, void* stream);
 
-/* One whole step: bin, density, gradient and force.  With the default
- * launch mode the three loops run in ONE persistent kernel: wavefronts pull
- * tile tasks from a device queue, and a box's gradient and force tasks wait
- * (per-box counters) until that box's density tasks are done.  Any of
- * go / fo may be NULL to skip that loop. */
+/* One whole step: bin, density, gradient and force (go / fo may be NULL to
+ * skip that loop).  The step is captured once into a HIP graph (on a
+ * stream the plan creates) and replayed on `stream` while the particle,
+ * output and workspace pointers, the sizes, the box data and the options
+ * stay the same; a change re-captures.  The box table is uploaded on
+ * `stream` at each capture.  Each loop is one persistent launch over the
+ * tiles of every box (the fine-graining answer of Sec. 4.4.3).  With
+ * SWSPH_PER_TASK_LAUNCH or SWSPH_TIMING the calls run eagerly instead.
+ * Same errors as the four calls it makes. */
 int swsph_step(swsph_plan* plan, const swsph_particles* p, swsph_density_out* d,
                swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream);
 

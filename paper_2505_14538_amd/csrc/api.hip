@@ -191,6 +191,10 @@ struct swsph_plan {
     void* ws = nullptr;
     Geometry G;
     uint64_t bin_id = 0;
+    // captured whole step (swsph_step): its key and the capture stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> gkey;
 };
 
 namespace {
@@ -363,7 +367,11 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
 }
 
 int swsph_plan_destroy(swsph_plan* pl) {
-    if (pl) delete pl->timer;
+    if (pl) {
+        delete pl->timer;
+        if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+        if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    }
     delete pl;
     return SWSPH_OK;
 }
@@ -389,8 +397,13 @@ int swsph_workspace_bytes(const swsph_plan* pl, int64_t n, int32_t n_box, const 
     return SWSPH_OK;
 }
 
-int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) {
-    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+}  // extern "C"
+
+namespace {
+
+// swsph_bin in three parts: host checks and geometry (plan state), the box
+// table upload, and the binning kernels (capturable: no host memory).
+int bin_prepare(swsph_plan* pl, const swsph_particles* p, void* ws) {
     int r = check_particles(pl, p, false);
     if (r) return r;
     if (!ws) return fail(SWSPH_E_ARG, "workspace is NULL");
@@ -404,13 +417,20 @@ int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) 
     pl->ws = ws;
     pl->binned = true;
     ++pl->bin_id;
-    hipStream_t s = (hipStream_t)stream;
-    BinPtrs b = ptrs_of(pl, ws);
+    return SWSPH_OK;
+}
+
+int bin_upload(swsph_plan* pl, hipStream_t s) {
+    BinPtrs b = ptrs_of(pl, pl->ws);
+    return hip_check(hipMemcpyAsync(b.boxtab, pl->G.boxes.data(), sizeof(BoxInfo) * pl->G.n_box,
+                                    hipMemcpyHostToDevice, s),
+                     "copy box table");
+}
+
+void bin_enqueue(swsph_plan* pl, const swsph_particles* p, hipStream_t s) {
+    const Geometry& G = pl->G;
+    BinPtrs b = ptrs_of(pl, pl->ws);
     launch_fill_u32(b.cnt, sizeof(Counters) / 4, 0u, s);
-    r = hip_check(hipMemcpyAsync(b.boxtab, pl->G.boxes.data(), sizeof(BoxInfo) * G.n_box,
-                                 hipMemcpyHostToDevice, s),
-                  "copy box table");
-    if (r) return r;
     launch_fill_u32(b.fine_count, G.n_fine + 1, 0u, s);
     const bool f64 = pl->cfg.dtype == SWSPH_F64;
     if (f64) launch_keys<double>(p, b.boxtab, b.keys, b.slot, b.fine_count, b.cnt, s);
@@ -426,6 +446,20 @@ int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) 
                              b.hs, s);
         launch_make_tiles<float>(b, s);
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int swsph_bin(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = bin_prepare(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = bin_upload(pl, s);
+    if (r) return r;
+    bin_enqueue(pl, p, s);
     return hip_check(hipGetLastError(), "swsph_bin launch");
 }
 
@@ -578,7 +612,50 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
 
 extern "C" {
 
-int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
+}  // extern "C"
+
+namespace {
+
+// Everything a captured step depends on: pointers, sizes, box data and the
+// execution options.  A different key means a new capture.
+std::vector<uint64_t> step_key(const swsph_plan* pl, const swsph_particles* p,
+                               const swsph_density_out* d, const swsph_gradient_out* go,
+                               const swsph_force_out* fo, const void* ws) {
+    std::vector<uint64_t> k;
+    auto P = [&](const void* v) { k.push_back((uint64_t)(uintptr_t)v); };
+    P(ws);
+    k.push_back((uint64_t)p->n);
+    k.push_back((uint64_t)p->n_box);
+    P(p->x); P(p->y); P(p->z); P(p->vx); P(p->vy); P(p->vz); P(p->u); P(p->m);
+    P(p->box_id); P(p->h);
+    for (int b = 0; b < p->n_box; ++b) {
+        uint64_t bits;
+        std::memcpy(&bits, &p->box_size[b], 8);
+        k.push_back(bits);
+        k.push_back(p->box_count ? (uint64_t)p->box_count[b] : (uint64_t)p->n);
+    }
+    P(d->h); P(d->rho); P(d->rho_dh); P(d->wcount); P(d->wcount_dh); P(d->div_v);
+    P(d->curl_x); P(d->curl_y); P(d->curl_z); P(d->f); P(d->nngb); P(d->iters);
+    P(go); if (go) { P(go->v_sig); P(go->lap_u); }
+    P(fo); if (fo) { P(fo->ax); P(fo->ay); P(fo->az); P(fo->dudt); P(fo->nint); }
+    const swsph_config& c = pl->cfg;
+    const double dv[6] = {c.eta, c.eps, c.gamma, c.alpha, c.beta, c.h_tol};
+    for (double v : dv) {
+        uint64_t bits;
+        std::memcpy(&bits, &v, 8);
+        k.push_back(bits);
+    }
+    k.push_back((uint64_t)c.h_max_iter);
+    k.push_back((uint64_t)c.dtype);
+    k.push_back((uint64_t)c.flags);
+    k.push_back((uint64_t)pl->tile);
+    k.push_back((uint64_t)pl->lds_cap);
+    k.push_back((uint64_t)pl->order);
+    k.push_back((uint64_t)pl->leaf_max);
+    return k;
+}
+
+int step_eager(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
                swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
     int r = swsph_bin(pl, p, ws, stream);
     if (r) return r;
@@ -593,6 +670,60 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
         if (r) return r;
     }
     return SWSPH_OK;
+}
+
+void drop_graph(swsph_plan* pl) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    pl->exec = nullptr;
+    pl->gkey.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    if (!d) return fail(SWSPH_E_ARG, "density output is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    // one launch per task reads the task count back, and timing records
+    // events: both run eagerly
+    if (pl->cfg.flags & (SWSPH_PER_TASK_LAUNCH | SWSPH_TIMING) || p->n == 0)
+        return step_eager(pl, p, d, go, fo, ws, stream);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint64_t> key = step_key(pl, p, d, go, fo, ws);
+    if (!pl->exec || key != pl->gkey) {
+        drop_graph(pl);
+        r = bin_prepare(pl, p, ws);
+        if (r) return r;
+        r = bin_upload(pl, s);
+        if (r) return r;
+        if (!pl->cap) {
+            r = hip_check(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking), "capture stream");
+            if (r) return r;
+        }
+        r = hip_check(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (r) return r;
+        bin_enqueue(pl, p, pl->cap);
+        int rr = swsph_density(pl, p, d, ws, pl->cap);
+        if (!rr && go) rr = swsph_gradient(pl, p, d, go, ws, pl->cap);
+        if (!rr && fo) rr = swsph_force(pl, p, d, fo, ws, pl->cap);
+        hipGraph_t g = nullptr;
+        r = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
+        if (!r && rr) r = rr;
+        if (!r) r = hip_check(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0), "instantiate");
+        if (g) (void)hipGraphDestroy(g);
+        if (r) {
+            drop_graph(pl);
+            return r;
+        }
+        pl->gkey = std::move(key);
+    } else {
+        ++pl->bin_id;
+    }
+    return hip_check(hipGraphLaunch(pl->exec, s), "graph launch");
 }
 
 int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
@@ -628,8 +759,117 @@ int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_d
 
 int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* stream,
                    const char* cache_path) {
-    (void)pl; (void)p; (void)ws; (void)stream; (void)cache_path;
-    return fail(SWSPH_E_ARG, "swsph_autotune: not available in this build");
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!ws) return fail(SWSPH_E_ARG, "workspace is NULL");
+    if (pl->cfg.flags & SWSPH_PER_TASK_LAUNCH)
+        return fail(SWSPH_E_ARG, "autotune times the batched launch; not for PER_TASK_LAUNCH");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    r = hip_check(hipGetDevice(&dev), "get device");
+    if (r) return r;
+    r = hip_check(hipGetDeviceProperties(&prop, dev), "device properties");
+    if (r) return r;
+    char key[640];
+    snprintf(key, sizeof key, "%s|n=%lld|boxes=%d|dtype=%d|flags=%u", prop.gcnArchName,
+             (long long)p->n, p->n_box, pl->cfg.dtype,
+             pl->cfg.flags & (SWSPH_FIXED_H | SWSPH_NO_VISC | SWSPH_FLAT_LAUNCH));
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            bool hit = false;
+            while (std::fgets(line, sizeof line, f)) {
+                char k2[640];
+                int t = 0, c = 0, o = 0;
+                if (std::sscanf(line, "%639s %d %d %d", k2, &t, &c, &o) == 4 &&
+                    std::strcmp(k2, key) == 0 && (t == 8 || t == 16 || t == 32 || t == 64) &&
+                    (c == 128 || c == 256 || c == 512) && (o == 0 || o == 1)) {
+                    pl->tile = t;
+                    pl->lds_cap = c;
+                    pl->order = o;
+                    hit = true;
+                }
+            }
+            std::fclose(f);
+            if (hit) return SWSPH_OK;
+        }
+    }
+    // The timed step writes its outputs into the adjoint region of the
+    // workspace (free outside swsph_force_backward); sizes follow a bin.
+    r = swsph_bin(pl, p, ws, stream);
+    if (r) return r;
+    const int64_t n = p->n;
+    const uint64_t tsz = pl->cfg.dtype == SWSPH_F64 ? 8 : 4;
+    char* a = (char*)ws + pl->G.lay.adj;
+    auto arr = [&](int k) { return (void*)(a + (uint64_t)k * tsz * (uint64_t)n); };
+    swsph_density_out d{arr(0), arr(1), arr(2), arr(3), arr(4), arr(5), arr(6), arr(7), arr(8),
+                        arr(9), (int32_t*)arr(10), (int32_t*)arr(11)};
+    swsph_gradient_out go{arr(12), arr(13)};
+    swsph_force_out fo{arr(14), arr(15), arr(16), arr(17), (int32_t*)arr(18)};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    r = hip_check(hipEventCreate(&e0), "event");
+    if (!r) r = hip_check(hipEventCreate(&e1), "event");
+    auto time_one = [&](int tile, int cap, int order, float& best_ms) -> int {
+        pl->tile = tile;
+        pl->lds_cap = cap;
+        pl->order = order;
+        float ms = 3.0e38f;
+        for (int rep = 0; rep < 2; ++rep) {
+            int q = hip_check(hipEventRecord(e0, s), "event record");
+            if (!q) q = swsph_step(pl, p, &d, &go, &fo, ws, stream);
+            if (!q) q = hip_check(hipEventRecord(e1, s), "event record");
+            if (!q) q = hip_check(hipEventSynchronize(e1), "event sync");
+            if (q) return q;
+            float t = 0.f;
+            q = hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed");
+            if (q) return q;
+            ms = std::min(ms, t);
+        }
+        swsph_stats st;
+        const int q = swsph_read_stats(pl, ws, &st, stream);
+        if (q) return q;
+        best_ms = ms;
+        return SWSPH_OK;
+    };
+    // coordinate descent: tile size, then LDS capacity, then task order
+    int bt = pl->tile, bc = pl->lds_cap, bo = pl->order;
+    float best = 3.0e38f;
+    if (!r) r = time_one(bt, bc, bo, best);
+    const int tiles[4] = {8, 16, 32, 64}, caps[3] = {128, 256, 512}, orders[2] = {0, 1};
+    for (int k = 0; k < 4 && !r; ++k) {
+        if (tiles[k] == bt) continue;
+        float t = 0.f;
+        r = time_one(tiles[k], bc, bo, t);
+        if (!r && t < best) { best = t; bt = tiles[k]; }
+    }
+    for (int k = 0; k < 3 && !r; ++k) {
+        if (caps[k] == bc) continue;
+        float t = 0.f;
+        r = time_one(bt, caps[k], bo, t);
+        if (!r && t < best) { best = t; bc = caps[k]; }
+    }
+    for (int k = 0; k < 2 && !r; ++k) {
+        if (orders[k] == bo) continue;
+        float t = 0.f;
+        r = time_one(bt, bc, orders[k], t);
+        if (!r && t < best) { best = t; bo = orders[k]; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    pl->tile = bt;
+    pl->lds_cap = bc;
+    pl->order = bo;
+    if (r) return r;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %d\n", key, bt, bc, bo);
+            std::fclose(f);
+        }
+    }
+    // leave the workspace binned with the chosen tiles
+    return swsph_bin(pl, p, ws, stream);
 }
 
 }  // extern "C"

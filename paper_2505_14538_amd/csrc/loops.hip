@@ -53,6 +53,9 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const T hedge = hstage * ((T)1 - (T)8 * tiny);  // largest h whose support is staged
     (void)L;
 
+    // a guess beyond the staged radius starts at its edge (the radius is
+    // capped below half the box)
+    if (!fixed && h > hedge) h = hedge;
     T lo_h = 0, hi_h = hstage;
     bool has_upper = false;
     bool conv = fixed || !act;
@@ -415,6 +418,24 @@ static int launch_loop(KArgs<T> a, int mode, int lds_cap, int queue_slot, hipStr
     return launch_loop_cap<LK, T, 128>(a, mode, queue_slot, s);
 }
 
+// Indices of the tiles flagged for a density fix-up (any order: tiles are
+// independent), one atomic per wavefront.
+__global__ void k_fix_list(const int32_t* __restrict__ tflag, Counters* __restrict__ cnt,
+                           int32_t* __restrict__ list) {
+    const int64_t nt = (int64_t)cnt->n_tiles;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nt; base += nth) {
+        const int64_t t = base + threadIdx.x;
+        const bool f = t < nt && tflag[t] != 0;
+        const unsigned long long m = ballot(f);
+        int at = 0;
+        if (lane_id() == 0 && m)
+            at = (int)atomicAdd(&cnt->n_fix, (unsigned long long)__popcll(m));
+        at = __shfl(at, 0, WAVE);
+        if (f) list[at + mbcnt(m)] = (int32_t)t;
+    }
+}
+
 // Density: the first pass, then up to three fix-up passes for tiles whose
 // Newton iteration needed a wider task list (the last one latches failures).
 template <typename T>
@@ -427,10 +448,18 @@ int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hi
     int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
     timer_end(sc.timer, 0, s);
     if (r || (sc.flags & SWSPH_FIXED_H)) return r;
+    // fix-up passes run over the list of flagged tiles only
+    a.order = b.tmpidx;
+    a.ntask = &b.cnt->n_fix;
     for (int pass = 1; pass <= 3 && !r; ++pass) {
+        launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
+        hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
+                           (const int32_t*)b.tflag, b.cnt, b.tmpidx);
         launch_tasks<T>(b, sc, 0, true, s);
         a.fixup = pass == 3 ? 2 : 1;
+        timer_begin(sc.timer, 0, s);
         r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, lds_cap, 0, s);
+        timer_end(sc.timer, 0, s);
     }
     return r;
 }

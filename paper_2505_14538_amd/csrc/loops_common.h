@@ -24,7 +24,8 @@ template <typename T>
 struct KArgs {
     const BoxInfo* boxtab;
     const Tile* tiles;
-    const int32_t* order;
+    const int32_t* order;      // task list: tile indices in queue order
+    const unsigned long long* ntask;  // its length (device)
     int64_t tile_cap;          // bound of the device tile count (cnt->n_tiles)
     int32_t task;              // per-task launch: the task to run
     const int32_t* leaf_cnt;
@@ -268,6 +269,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
     a.order = b.order;
+    a.ntask = &b.cnt->n_tiles;
     a.tile_cap = b.tile_cap;
     a.task = 0;
     a.leaf_cnt = b.leaf_cnt;
@@ -299,19 +301,23 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
 }
 
 // Task dispatch inside a loop kernel: the persistent queue (every wavefront
-// pops tile tasks until the queue is drained; at most tile_cap + 1 pops),
-// the static round-robin schedule, or the one task of a per-task launch.
+// pops QCHUNK consecutive tasks at a time until the list is drained; at
+// most tile_cap + 1 pops), the static round-robin schedule, or the one task
+// of a per-task launch.
+constexpr int QCHUNK = 4;
+
 template <typename T, class Run>
 __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&& run) {
     const int wave = threadIdx.x / WAVE;
-    const int64_t nt = (int64_t)a.cnt->n_tiles;
+    const int64_t nt = (int64_t)*a.ntask;
     if (mode == MODE_QUEUE) {
         for (int64_t guard = 0; guard <= a.tile_cap; ++guard) {
-            int t = 0;
-            if (lane_id() == 0) t = (int)atomicAdd(a.queue, 1ull);
-            t = uniform(__shfl(t, 0, WAVE));
-            if (t < 0 || t >= nt) break;
-            run(a.order[t]);
+            int t0 = 0;
+            if (lane_id() == 0) t0 = (int)atomicAdd(a.queue, (unsigned long long)QCHUNK);
+            t0 = uniform(__shfl(t0, 0, WAVE));
+            if (t0 < 0 || t0 >= nt) break;
+            const int t1 = (int)min((int64_t)t0 + QCHUNK, nt);
+            for (int t = t0; t < t1; ++t) run(a.order[t]);
         }
     } else if (mode == MODE_FLAT) {
         const int64_t nw = (int64_t)gridDim.x * WPB;
@@ -352,7 +358,7 @@ int launch_with(void (*kern)(KArgs<T>, int), KArgs<T> a, int mode, int queue_slo
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, a, mode);
     } else {
         unsigned long long nt = 0;
-        if (hipMemcpyAsync(&nt, &a.cnt->n_tiles, sizeof nt, hipMemcpyDeviceToHost, s) !=
+        if (hipMemcpyAsync(&nt, a.ntask, sizeof nt, hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return -1;

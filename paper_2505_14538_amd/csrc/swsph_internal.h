@@ -57,7 +57,8 @@ struct Counters {
     unsigned long long queue[8];       // task-queue heads of the loops
     unsigned long long leaf_need;      // leaves requested by the last task build
     unsigned long long n_tiles;        // tiles made by the last bin
-    unsigned long long reserved[8];
+    unsigned long long n_fix;          // tiles listed for the current density fix-up pass
+    unsigned long long reserved[7];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };

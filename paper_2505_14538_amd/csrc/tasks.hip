@@ -52,7 +52,8 @@ __device__ void task_one(const TArgs<T>& a, SearchMem& m, const Tile& tl, int64_
         const T hmax = wave_max(h);
         R = (float)(a.eps * hmax * a.margin);
         if (!(R < Rcap)) {
-            if (MODE != 0 && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
+            // fixed supports (every loop but the Newton density search) must fit
+            if ((MODE != 0 || a.margin == (T)1) && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
             R = Rcap;
         }
         if (!(R > 0.f)) R = Rcap;

@@ -315,20 +315,32 @@ class Plan:
                                 self._ws_ptr(), _stream()))
         return o
 
-    def step(self, p: DeviceParticles, gradient: bool = True, force: bool = True):
-        """bin + density + gradient + force in one call (fused persistent kernel)."""
+    def step(self, p: DeviceParticles, gradient: bool = True, force: bool = True, out=None):
+        """bin + density + gradient + force in one call.  The library captures
+        the whole step in a HIP graph and replays it while the particle and
+        output buffers stay the same, so by default the outputs are buffers
+        the plan keeps and overwrites at the next step (copy what must
+        survive); `out` = (d, g, f) dicts of caller tensors instead."""
         torch = _torch()
         self.ensure_workspace(p)
         n = p.n
-        d = {k: self._alloc(n) for k in ("h", "rho", "rho_dh", "wcount", "wcount_dh", "div_v",
-                                          "curl_x", "curl_y", "curl_z", "f")}
-        d["nngb"] = self._alloc(n, torch.int32)
-        d["iters"] = self._alloc(n, torch.int32)
-        g = {"v_sig": self._alloc(n), "lap_u": self._alloc(n)} if gradient else None
-        f = None
-        if force:
-            f = {k: self._alloc(n) for k in ("ax", "ay", "az", "dudt")}
-            f["nint"] = self._alloc(n, torch.int32)
+        if out is None:
+            key = (n, bool(gradient), bool(force), self.dtype)
+            if getattr(self, "_step_key", None) != key:
+                d = {k: self._alloc(n) for k in ("h", "rho", "rho_dh", "wcount", "wcount_dh",
+                                                  "div_v", "curl_x", "curl_y", "curl_z", "f")}
+                d["nngb"] = self._alloc(n, torch.int32)
+                d["iters"] = self._alloc(n, torch.int32)
+                g = {"v_sig": self._alloc(n), "lap_u": self._alloc(n)} if gradient else None
+                f = None
+                if force:
+                    f = {k: self._alloc(n) for k in ("ax", "ay", "az", "dudt")}
+                    f["nint"] = self._alloc(n, torch.int32)
+                self._step_out = (d, g, f)
+                self._step_key = key
+            d, g, f = self._step_out
+        else:
+            d, g, f = out
         dc = self._dens_c(d)
         gc = GradientOut(_ptr(g["v_sig"]), _ptr(g["lap_u"])) if g else None
         fc = ForceOut(**{k: _ptr(v) for k, v in f.items()}) if f else None
