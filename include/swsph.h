@@ -105,7 +105,7 @@ typedef struct swsph_config {
     int32_t dtype;       /* swsph_dtype of every particle array */
     uint32_t flags;      /* SWSPH_* flags above */
     int32_t tile;        /* most i-particles per task: 8, 16, 32 or 64 (0: 32) */
-    int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 512) */
+    int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 128) */
     int32_t order;       /* task order: 0 cost-descending (default), 1 Morton */
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: auto) */
     int32_t reserved[5];

@@ -56,7 +56,10 @@ template <typename T> struct AdjPtrs {
 
 template <typename T, int CAP>
 __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
     const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
@@ -82,10 +85,10 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     T gx = 0, gy = 0, gz = 0, gvx = 0, gvy = 0, gvz = 0;
     T gm = 0, gA = 0, gf = 0, gc = 0, grho = 0, gh = 0;
     // pairs with r = 0 (the self pair, coincident particles) contribute nothing
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> s0 = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
-        return act && r2 < max(H2, s0.w) && r2 > (T)0;
+        return ok && act && r2 < max(H2, s0.w) && r2 > (T)0;
     };
     auto body = [&](int k) {
         const V4<T> s0 = m.s[0][k];
@@ -198,7 +201,10 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
 
 template <typename T, int CAP>
 __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
     const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
@@ -219,10 +225,10 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const V4<T> ai = a.aux4[i];  // (m_i, rho_bar_i, rho'_bar_i, 1/H_i)
     const T rb = ai.y, rpb = ai.z, mi = pi.w;
     T gx = 0, gy = 0, gz = 0, gm = 0, gh = 0;
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> s0 = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
-        return r2 < H2 || (act && r2 < s0.w);
+        return ok && (r2 < H2 || (act && r2 < s0.w));
     };
     auto body = [&](int k) {
         const V4<T> s0 = m.s[0][k];
@@ -282,7 +288,10 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
 
 template <typename T, int CAP>
 __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
     const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
@@ -302,10 +311,10 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     AdjPtrs<T> J{a.out, a.n};
     const T lhi = a.aux4[i].x;  // lambda_i h_i^3
     T gx = 0, gy = 0, gz = 0;
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> s0 = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - s0.x, pi.y - s0.y, pi.z - s0.z);
-        return (r2 < H2 || (act && r2 < s0.w)) && r2 > (T)0;
+        return ok && (r2 < H2 || (act && r2 < s0.w)) && r2 > (T)0;
     };
     auto body = [&](int k) {
         const V4<T> s0 = m.s[0][k];

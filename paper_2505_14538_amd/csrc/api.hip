@@ -358,7 +358,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
     pl->cfg = *cfg;
     pl->tile = cfg->tile ? cfg->tile : 32;
-    pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 512;
+    pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
     if (cfg->flags & SWSPH_TIMING) pl->timer = new (std::nothrow) swsph::Timer();

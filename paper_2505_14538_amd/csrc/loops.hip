@@ -27,7 +27,10 @@ namespace swsph {
 
 template <typename T, int CAP>
 __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     if (a.fixup && a.tflag[t] == 0) return;
     const int lane = lane_id();
@@ -69,9 +72,9 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     T H = eps * h;
     T H2 = act ? mul_unfused(H, H) : (T)-1;
     T invH = (T)1 / H;
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
-        return dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];
@@ -123,9 +126,19 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
                 if (!has_upper && hn >= hedge) {
                     // the step leaves the staged set: first try its edge; if
                     // the root lies beyond, the tile gets a fix-up pass
-                    if (h < hedge) h = hedge;
-                    else if (R >= Rcap) { failed = true; conv = true; }
-                    else { pend = true; want = hn; }
+                    if (h < hedge) {
+                        h = hedge;
+                    } else if (R >= Rcap) {
+                        failed = true;
+                        conv = true;
+                    } else {
+                        // next radius from the local h^3 scaling of G (a Newton
+                        // step from below can overshoot far), grown at most 2x
+                        // per pass
+                        pend = true;
+                        const T grow = (T)1.05 * cbrt(Tt / G);
+                        want = h * min((T)2, max((T)1.02, grow));
+                    }
                 } else if (fabs(hn - h) <= tiny * h) {
                     conv = true;
                 } else {
@@ -212,7 +225,10 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
 
 template <typename T, int CAP>
 __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
     const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
@@ -234,10 +250,10 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     T vsig = (T)2 * ci, lap = 0;
     unsigned long long tested = 0;
     int inside = 0;
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        return r2 < H2 && r2 > (T)0;
+        return ok && r2 < H2 && r2 > (T)0;
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];
@@ -252,7 +268,8 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
         const T s = ci + vj.w - a.beta * mu;
         vsig = s > vsig ? s : vsig;
         const T t1 = (T)1 - q;
-        const T gq = q < (T)0.5 ? (T)18 * q - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
+        const T gin = (T)18 * q - (T)12, gout = (T)-6 * t1 * t1 * (H * inv_r);
+        const T gq = q < (T)0.5 ? gin : gout;
         lap += sj.w * (ui - uj) * gq;
         ++inside;
     };
@@ -282,7 +299,10 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
 
 template <typename T, int CAP>
 __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
-    const Tile tl = a.tiles[t];
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
     const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
@@ -312,10 +332,10 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     // coincident pairs (r = 0) add nothing to a and du/dt, so only r > 0 goes
     // to the body, and nint = hits - 1 (the self pair is staged exactly once)
     int hits = 0;
-    auto test = [&](int k) {
+    auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        const bool in = act && r2 < max(H2, sj.w);
+        const bool in = ok && act && r2 < max(H2, sj.w);
         hits += in ? 1 : 0;
         return in && r2 > (T)0;
     };
@@ -448,9 +468,10 @@ int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hi
     int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
     timer_end(sc.timer, 0, s);
     if (r || (sc.flags & SWSPH_FIXED_H)) return r;
-    // fix-up passes run over the list of flagged tiles only
+    // fix-up passes run over the list of flagged tiles only (any order)
     a.order = b.tmpidx;
     a.ntask = &b.cnt->n_fix;
+    a.xcd_split = 0;
     for (int pass = 1; pass <= 3 && !r; ++pass) {
         launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
         hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
@@ -528,38 +549,25 @@ template void launch_prep_dens<double>(const BinPtrs&, const Scheme&, const swsp
 // Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
 // of every box: fine cells by atomic max over particles, then each fine cell
 // pushes its value up while it raises the parent.
+// Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
+// of every box: each particle raises its fine cell and walks up while it
+// raises the parent (most walks stop after a level or two).
 template <typename T>
-__global__ void k_hmax_fine(int64_t n, const int32_t* __restrict__ perm,
-                            const uint32_t* __restrict__ keys, int32_t n_box,
-                            const BoxInfo* __restrict__ boxtab, const T* __restrict__ hs, T eps,
-                            float* __restrict__ pyr) {
+__global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
+                       const uint32_t* __restrict__ keys, int32_t n_box,
+                       const BoxInfo* __restrict__ boxtab, const T* __restrict__ hs, T eps,
+                       float* __restrict__ pyr) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int32_t p = perm[s];
     const BoxInfo bi = boxtab[box_of_sorted(s, n_box, boxtab)];
+    const int k = bi.k < 10 ? bi.k : 10;
     const uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
     const float H = (float)(eps * hs[s]) * (1.0f + 1e-6f);
-    atomicMax((int*)&pyr[bi.pyr_off + pyr_level_off(bi.k) + mort], __float_as_int(H));
-}
-
-__global__ void k_hmax_up(int64_t n_fine, int32_t n_box, const BoxInfo* __restrict__ boxtab,
-                          float* __restrict__ pyr) {
-    int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (f >= n_fine) return;
-    int lo = 0, hi = n_box - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (boxtab[mid].fine_off <= f) lo = mid; else hi = mid - 1;
-    }
-    const BoxInfo bi = boxtab[lo];
-    const int k = bi.k < 10 ? bi.k : 10;
-    const uint32_t mort = (uint32_t)(f - bi.fine_off);
-    const float v = pyr[bi.pyr_off + pyr_level_off(k) + mort];
-    if (!(v > 0.f)) return;
-    for (int l = k - 1; l >= 0; --l) {
-        float* pp = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
-        if (*pp >= v) break;
-        atomicMax((int*)pp, __float_as_int(v));
+    for (int l = k; l >= 0; --l) {
+        float* c = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
+        if (*c >= H) break;
+        atomicMax((int*)c, __float_as_int(H));
     }
 }
 
@@ -567,11 +575,8 @@ template <typename T>
 void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s) {
     launch_fill_u32(b.hmaxpyr, b.n_pyr, 0u, s);
     if (b.n <= 0) return;
-    hipLaunchKernelGGL(k_hmax_fine<T>, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, s, b.n,
-                       b.perm, b.keys, b.n_box, b.boxtab, (const T*)b.hs,
-                       (T)sc.eps, b.hmaxpyr);
-    hipLaunchKernelGGL(k_hmax_up, dim3((unsigned)((b.n_fine + 255) / 256)), dim3(256), 0, s,
-                       b.n_fine, b.n_box, b.boxtab, b.hmaxpyr);
+    hipLaunchKernelGGL(k_hmax<T>, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, s, b.n,
+                       b.perm, b.keys, b.n_box, b.boxtab, (const T*)b.hs, (T)sc.eps, b.hmaxpyr);
 }
 template void launch_hmax_pyramid<float>(const BinPtrs&, const Scheme&, hipStream_t);
 template void launch_hmax_pyramid<double>(const BinPtrs&, const Scheme&, hipStream_t);

@@ -43,7 +43,8 @@ struct KArgs {
     int32_t* iout;             // sorted int outputs, arrays of n
     int64_t n;
     Counters* cnt;
-    unsigned long long* queue;
+    unsigned long long* queue;        // NXCD queue heads
+    int32_t xcd_split;                // queue: one Morton segment of the task list per XCD
     T eta, eps, gamma, alpha, beta, h_tol;
     int32_t h_max_iter;
     uint32_t flags;
@@ -78,29 +79,49 @@ template <typename V> __device__ __forceinline__ V stream_max(V v, int tile) {
 // Pair loop over the staged j-particles with per-lane compaction.  Lane
 // (i-slot, stream js) runs the distance test over the staged indices
 // js, js + S, ...; the hits go, in index order, to the lane's own list in
-// LDS, and whenever some list is full (and at the end) every lane runs the
-// pair body over its list with the wavefront in step.  The body thus runs
-// with nearly all lanes busy instead of under the divergence of the test
-// (only ~1 in 5 tested pairs lies inside the support), and each lane still
-// accumulates its pairs in staged order, so results do not depend on LC.
+// LDS, and whenever some list could overflow (and at the end) every lane
+// runs the pair body over its list with the wavefront in step.  The body
+// thus runs with nearly all lanes busy instead of under the divergence of
+// the test (only a few of the tested pairs lie inside the support), and
+// each lane still accumulates its pairs in staged order, so results do not
+// depend on LC.  Tests go PL_U at a time (their LDS reads issue together),
+// the body two at a time (the second pair's reads overlap the first's
+// arithmetic); loop control is wavefront-uniform.  test(k, ok) must return
+// false when !ok (k is then a valid but repeated index).
+constexpr int PL_U = 4;
+
 template <class WM, class Test, class Body>
 __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& test,
                                           Body&& body) {
     const int lane = lane_id();
+    ns = uniform(ns);
+    S = uniform(S);
     int c = 0;
     auto drain = [&]() {
-        for (int e = 0; ballot(e < c) != 0ull; ++e) {
-            if (e < c) body((int)m.lst[e][lane]);
+        for (int e = 0; ballot(e < c) != 0ull; e += 2) {
+            const int k0 = e < c ? (int)m.lst[e][lane] : -1;
+            const int k1 = e + 1 < c ? (int)m.lst[e + 1][lane] : -1;
+            if (k0 >= 0) body(k0);
+            if (k1 >= 0) body(k1);
         }
         c = 0;
     };
-    for (int k0 = 0; k0 < ns; k0 += S) {
-        const int k = k0 + js;
-        if (k < ns && test(k)) {
-            m.lst[c][lane] = (uint16_t)k;
-            ++c;
+    const int step = S * PL_U;
+    for (int k0 = 0; k0 < ns; k0 += step) {
+        bool hit[PL_U];
+#pragma unroll
+        for (int u = 0; u < PL_U; ++u) {
+            const int k = k0 + js + u * S;
+            hit[u] = test(k < ns ? k : ns - 1, k < ns);
         }
-        if (ballot(c == LC) != 0ull) drain();
+#pragma unroll
+        for (int u = 0; u < PL_U; ++u) {
+            if (hit[u]) {
+                m.lst[c][lane] = (uint16_t)(k0 + js + u * S);
+                ++c;
+            }
+        }
+        if (ballot(c > LC - PL_U) != 0ull) drain();
     }
     drain();
 }
@@ -236,23 +257,23 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
 
 template <typename T>
 __device__ __forceinline__ void m4_terms(T q, T inv_q, T& w, T& s1, T& g) {
+    // both pieces, then a select: no divergent branch in the pair body
     const T t = (T)1 - q;
     const T q2 = q * q;
-    if (q < (T)0.5) {
-        w = (T)1 + q2 * ((T)6 * q - (T)6);
-        s1 = (T)3 + q2 * ((T)36 * q - (T)30);
-        g = (T)18 * q - (T)12;
-    } else {
-        const T t2 = t * t;
-        w = (T)2 * t2 * t;
-        s1 = (T)6 * t2 * ((T)1 - (T)2 * q);
-        g = (T)-6 * t2 * inv_q;
-    }
+    const T t2 = t * t;
+    const bool in = q < (T)0.5;
+    const T wi = (T)1 + q2 * ((T)6 * q - (T)6), wo = (T)2 * t2 * t;
+    const T si = (T)3 + q2 * ((T)36 * q - (T)30), so = (T)6 * t2 * ((T)1 - (T)2 * q);
+    const T gi = (T)18 * q - (T)12, go = (T)-6 * t2 * inv_q;
+    w = in ? wi : wo;
+    s1 = in ? si : so;
+    g = in ? gi : go;
 }
 // w'(q)
 template <typename T> __device__ __forceinline__ T m4_dw(T q) {
     const T t = (T)1 - q;
-    return q < (T)0.5 ? q * ((T)18 * q - (T)12) : (T)-6 * t * t;
+    const T a = q * ((T)18 * q - (T)12), b = (T)-6 * t * t;
+    return q < (T)0.5 ? a : b;
 }
 
 __device__ __forceinline__ TileGeom geom_of(const Tile& tl) {
@@ -288,6 +309,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.n = b.n;
     a.cnt = b.cnt;
     a.queue = nullptr;
+    a.xcd_split = sc.order == 1;
     a.eta = (T)sc.eta;
     a.eps = (T)sc.eps;
     a.gamma = (T)sc.gamma;
@@ -300,24 +322,45 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     return a;
 }
 
-// Task dispatch inside a loop kernel: the persistent queue (every wavefront
-// pops QCHUNK consecutive tasks at a time until the list is drained; at
-// most tile_cap + 1 pops), the static round-robin schedule, or the one task
-// of a per-task launch.
+// Task dispatch inside a loop kernel.
+//  * queue: every wavefront pops QCHUNK consecutive tasks at a time until the
+//    list is drained (at most tile_cap + 1 pops per list).  With xcd_split
+//    the list (in Morton order) is cut into NXCD contiguous segments and a
+//    workgroup starts on the segment of its XCD (workgroups are dealt to the
+//    XCDs round-robin), so each XCD's L2 cache sees a compact region of the
+//    box; a wavefront whose segment is drained helps the next ones.
+//  * flat: the static round-robin schedule.
+//  * per-task: the one task of the launch.
 constexpr int QCHUNK = 4;
+constexpr int NXCD = 8;
+
+template <class Run>
+__device__ __forceinline__ void pop_segment(unsigned long long* head, int64_t b, int64_t e,
+                                            int64_t cap, const int32_t* order, Run&& run) {
+    for (int64_t guard = 0; guard <= cap; ++guard) {
+        int t0 = 0;
+        if (lane_id() == 0) t0 = (int)atomicAdd(head, (unsigned long long)QCHUNK);
+        const int64_t s0 = b + uniform(__shfl(t0, 0, WAVE));
+        if (s0 >= e) break;
+        const int64_t s1 = min(s0 + QCHUNK, e);
+        for (int64_t t = s0; t < s1; ++t) run(order[t]);
+    }
+}
 
 template <typename T, class Run>
 __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&& run) {
     const int wave = threadIdx.x / WAVE;
     const int64_t nt = (int64_t)*a.ntask;
     if (mode == MODE_QUEUE) {
-        for (int64_t guard = 0; guard <= a.tile_cap; ++guard) {
-            int t0 = 0;
-            if (lane_id() == 0) t0 = (int)atomicAdd(a.queue, (unsigned long long)QCHUNK);
-            t0 = uniform(__shfl(t0, 0, WAVE));
-            if (t0 < 0 || t0 >= nt) break;
-            const int t1 = (int)min((int64_t)t0 + QCHUNK, nt);
-            for (int t = t0; t < t1; ++t) run(a.order[t]);
+        if (a.xcd_split) {
+            const int x0 = blockIdx.x % NXCD;
+            for (int y = 0; y < NXCD; ++y) {
+                const int x = (x0 + y) % NXCD;
+                pop_segment(&a.queue[x], nt * x / NXCD, nt * (x + 1) / NXCD, a.tile_cap, a.order,
+                            run);
+            }
+        } else {
+            pop_segment(&a.queue[0], 0, nt, a.tile_cap, a.order, run);
         }
     } else if (mode == MODE_FLAT) {
         const int64_t nw = (int64_t)gridDim.x * WPB;
@@ -344,9 +387,9 @@ int launch_with(void (*kern)(KArgs<T>, int), KArgs<T> a, int mode, int queue_slo
         attr_set = true;
     }
     if (a.tile_cap <= 0) return 0;
-    a.queue = &a.cnt->queue[queue_slot];
+    a.queue = a.cnt->queue[queue_slot];
     if (mode == MODE_QUEUE || mode == MODE_FLAT) {
-        if (mode == MODE_QUEUE) launch_fill_u32(a.queue, 2, 0u, s);
+        if (mode == MODE_QUEUE) launch_fill_u32(a.queue, 2 * NXCD, 0u, s);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WPB * WAVE,
                                                          shm) != hipSuccess)

@@ -54,7 +54,7 @@ struct Counters {
     unsigned long long newton_failed;
     unsigned long long leaves;
     unsigned long long restages;
-    unsigned long long queue[8];       // task-queue heads of the loops
+    unsigned long long queue[4][8];    // task-queue heads per loop (8: one per XCD segment)
     unsigned long long leaf_need;      // leaves requested by the last task build
     unsigned long long n_tiles;        // tiles made by the last bin
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
