@@ -131,7 +131,7 @@ def run(args):
     nngb = d["nngb"].to(torch.int64).sum().item()
     nint = f["nint"].to(torch.int64).sum().item()
     P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
-    sweeps = st["newton_sweeps"] / max(1, st["n_tiles"])   # counters cover the last step
+    sweeps = st["newton_sweeps"] / max(1, st["n_tiles_dens"])   # counters cover the last step
     value = (P_d + P_f) / t_step
     flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
     frac_peak = flops / t_step / PEAK_FP32

@@ -104,11 +104,13 @@ typedef struct swsph_config {
     int32_t h_max_iter;  /* Newton sweeps before SWSPH_ST_NEWTON is latched */
     int32_t dtype;       /* swsph_dtype of every particle array */
     uint32_t flags;      /* SWSPH_* flags above */
-    int32_t tile;        /* most i-particles per task: 8, 16, 32 or 64 (0: 32) */
+    int32_t tile;        /* most i-particles per gradient/force task: 8, 16, 32, 64 (0: 64) */
     int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 128) */
-    int32_t order;       /* task order: 0 cost-descending (default), 1 Morton */
+    int32_t order;       /* task order: 0 cost-descending, 1 Morton cut into one
+                            segment per XCD (default) */
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: auto) */
-    int32_t reserved[5];
+    int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 8) */
+    int32_t reserved[4];
 } swsph_config;
 
 /* Particle set.  Positions must lie in [0, box_size[b]) of their box b.
@@ -164,15 +166,16 @@ typedef struct swsph_input_grad {
 
 typedef struct swsph_stats {
     uint32_t status;             /* SWSPH_ST_* bits latched since the last bin */
-    uint32_t n_tiles;            /* tile tasks of the last bin */
+    uint32_t n_tiles;            /* gradient/force tile tasks of the last bin */
     uint64_t pairs_tested[4];    /* candidate pairs tested: density sweep, gradient, force, backward */
     uint64_t pairs_inside[4];    /* pairs inside the support (useful pairs) */
-    uint64_t newton_sweeps;      /* sum over tiles of density sweeps */
+    uint64_t newton_sweeps;      /* sum over density tiles of their sweeps */
     uint32_t newton_max;         /* largest sweep count of a tile */
     uint32_t newton_failed;      /* particles whose h did not converge */
     uint64_t leaves;             /* cells emitted by the task searches */
     uint64_t restages;           /* density tiles that widened their search */
-    uint64_t reserved[6];
+    uint64_t n_tiles_dens;       /* density tile tasks of the last bin */
+    uint64_t reserved[5];
 } swsph_stats;
 
 typedef struct swsph_plan swsph_plan;
@@ -266,7 +269,7 @@ int swsph_reset_timers(swsph_plan* plan);
 
 /* The tuning the plan will use: tile, lds_cap, order, leaf_max. */
 int swsph_plan_get_tuning(const swsph_plan* plan, int32_t* tile, int32_t* lds_cap,
-                          int32_t* order, int32_t* leaf_max);
+                          int32_t* order, int32_t* leaf_max, int32_t* tile_dens);
 
 #ifdef __cplusplus
 }

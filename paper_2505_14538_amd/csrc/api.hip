@@ -40,7 +40,8 @@ uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 struct Geometry {
     int64_t n = 0;
     int32_t n_box = 0;
-    int32_t tile = 32;
+    int32_t tile = 64;      // most particles per gradient/force tile
+    int32_t tile_d = 8;     // most particles per density tile
     int64_t tile_cap = 0;   // most tiles the bin can make (one per particle)
     int64_t n_fine = 0, n_pyr = 0;
     int64_t leaf_cap = 0;
@@ -65,7 +66,7 @@ int choose_k(int64_t nb) {
 }
 
 int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_count,
-                   const double* box_size, int tile, int tsz) {
+                   const double* box_size, int tile, int tile_d, int tsz) {
     if (n < 0) return fail(SWSPH_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
     if (n > (int64_t(1) << 26)) return fail(SWSPH_E_ARG, "n too large (max 2^26)");
     if (n_box < 1) return fail(SWSPH_E_ARG, "n_box must be >= 1");
@@ -74,6 +75,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     G.n = n;
     G.n_box = n_box;
     G.tile = tile;
+    G.tile_d = tile_d;
     G.tsz = tsz;
     G.boxes.assign(n_box, BoxInfo{});
     int64_t start = 0, fine = 0, pyr = 0, sum = 0;
@@ -130,6 +132,8 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.hmaxpyr = take(4 * (uint64_t)pyr);
     l.tiles = take(sizeof(Tile) * (uint64_t)toff);
     l.order = take(4 * (uint64_t)toff);
+    l.tiles_d = take(sizeof(Tile) * (uint64_t)toff);
+    l.order_d = take(4 * (uint64_t)toff);
     l.ord_table = take(4 * (uint64_t)order_table_size(toff));
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.leaf_cnt = take(4 * (uint64_t)(toff + 1));
@@ -150,6 +154,15 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
 }
 
 }  // namespace
+
+// The bin as the density loop sees it: its own tile set.
+BinPtrs swsph::density_view(const BinPtrs& b) {
+    BinPtrs d = b;
+    d.tiles = b.tiles_d;
+    d.order = b.order_d;
+    d.ntiles = &b.cnt->n_tiles_d;
+    return d;
+}
 
 // Pools of HIP event pairs, one list per loop kind.
 struct swsph::Timer {
@@ -186,7 +199,7 @@ void swsph::timer_end(Timer* t, int loop, hipStream_t s) {
 struct swsph_plan {
     swsph_config cfg;
     swsph::Timer* timer = nullptr;
-    int32_t tile, lds_cap, order, leaf_max;
+    int32_t tile, tile_d, lds_cap, order, leaf_max;
     bool binned = false;
     void* ws = nullptr;
     Geometry G;
@@ -209,6 +222,9 @@ int check_config(const swsph_config* c) {
     if (c->dtype != SWSPH_F32 && c->dtype != SWSPH_F64) return fail(SWSPH_E_ARG, "bad dtype");
     if (c->tile != 0 && c->tile != 8 && c->tile != 16 && c->tile != 32 && c->tile != 64)
         return fail(SWSPH_E_ARG, "tile must be 0, 8, 16, 32 or 64");
+    if (c->tile_dens != 0 && c->tile_dens != 8 && c->tile_dens != 16 && c->tile_dens != 32 &&
+        c->tile_dens != 64)
+        return fail(SWSPH_E_ARG, "tile_dens must be 0, 8, 16, 32 or 64");
     if (c->lds_cap != 0 && c->lds_cap != 128 && c->lds_cap != 256 && c->lds_cap != 512)
         return fail(SWSPH_E_ARG, "lds_cap must be 0, 128, 256 or 512");
     if (c->order != 0 && c->order != 1) return fail(SWSPH_E_ARG, "order must be 0 or 1");
@@ -273,6 +289,10 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.hmaxpyr = (float*)(w + l.hmaxpyr);
     b.tiles = (Tile*)(w + l.tiles);
     b.order = (int32_t*)(w + l.order);
+    b.ntiles = &b.cnt->n_tiles;
+    const bool same = pl->G.tile_d == pl->G.tile;
+    b.tiles_d = same ? b.tiles : (Tile*)(w + l.tiles_d);
+    b.order_d = same ? b.order : (int32_t*)(w + l.order_d);
     b.ord_table = (int32_t*)(w + l.ord_table);
     b.ord_base = (int32_t*)(w + l.ord_base);
     b.leaf_cnt = (int32_t*)(w + l.leaf_cnt);
@@ -292,6 +312,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.n_box = pl->G.n_box;
     b.tile_cap = pl->G.tile_cap;
     b.tile = pl->G.tile;
+    b.tile_d = pl->G.tile_d;
     b.n_fine = pl->G.n_fine;
     b.n_pyr = pl->G.n_pyr;
     return b;
@@ -345,7 +366,7 @@ void swsph_config_default(swsph_config* c) {
     c->flags = 0;
     c->tile = 0;
     c->lds_cap = 0;
-    c->order = 0;
+    c->order = 1;
     c->leaf_max = 0;
 }
 
@@ -357,7 +378,8 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     swsph_plan* pl = new (std::nothrow) swsph_plan();
     if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
     pl->cfg = *cfg;
-    pl->tile = cfg->tile ? cfg->tile : 32;
+    pl->tile = cfg->tile ? cfg->tile : 64;
+    pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 8;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
@@ -377,9 +399,10 @@ int swsph_plan_destroy(swsph_plan* pl) {
 }
 
 int swsph_plan_get_tuning(const swsph_plan* pl, int32_t* tile, int32_t* lds_cap, int32_t* order,
-                          int32_t* leaf_max) {
+                          int32_t* leaf_max, int32_t* tile_dens) {
     if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
     if (tile) *tile = pl->tile;
+    if (tile_dens) *tile_dens = pl->tile_d;
     if (lds_cap) *lds_cap = pl->lds_cap;
     if (order) *order = pl->order;
     if (leaf_max) *leaf_max = pl->leaf_max;
@@ -390,7 +413,7 @@ int swsph_workspace_bytes(const swsph_plan* pl, int64_t n, int32_t n_box, const 
                           const double* box_size, uint64_t* bytes) {
     if (!pl || !bytes) return fail(SWSPH_E_ARG, "plan and bytes are required");
     Geometry G;
-    int r = build_geometry(G, n, n_box, box_count, box_size, pl->tile,
+    int r = build_geometry(G, n, n_box, box_count, box_size, pl->tile, pl->tile_d,
                            pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
     if (r) return r;
     *bytes = G.lay.total;
@@ -411,7 +434,7 @@ int bin_prepare(swsph_plan* pl, const swsph_particles* p, void* ws) {
     Geometry G;
     const int64_t one = p->n;
     r = build_geometry(G, p->n, p->n_box, p->box_count ? p->box_count : &one, p->box_size,
-                       pl->tile, pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
+                       pl->tile, pl->tile_d, pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
     if (r) return r;
     pl->G = G;
     pl->ws = ws;
@@ -600,6 +623,7 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
     out->newton_failed = (uint32_t)c.newton_failed;
     out->leaves = c.leaves;
     out->restages = c.restages;
+    out->n_tiles_dens = c.n_tiles_d;
     if (c.status & SWSPH_ST_DOMAIN) return fail(SWSPH_E_DOMAIN, "a particle lies outside its box");
     if (c.status & SWSPH_ST_REACH) return fail(SWSPH_E_REACH, "a support radius reaches half a box");
     if (c.status & SWSPH_ST_CAPACITY) return fail(SWSPH_E_CAPACITY, "internal capacity exceeded");
@@ -649,6 +673,7 @@ std::vector<uint64_t> step_key(const swsph_plan* pl, const swsph_particles* p,
     k.push_back((uint64_t)c.dtype);
     k.push_back((uint64_t)c.flags);
     k.push_back((uint64_t)pl->tile);
+    k.push_back((uint64_t)pl->tile_d);
     k.push_back((uint64_t)pl->lds_cap);
     k.push_back((uint64_t)pl->order);
     k.push_back((uint64_t)pl->leaf_max);
@@ -782,11 +807,13 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
             bool hit = false;
             while (std::fgets(line, sizeof line, f)) {
                 char k2[640];
-                int t = 0, c = 0, o = 0;
-                if (std::sscanf(line, "%639s %d %d %d", k2, &t, &c, &o) == 4 &&
-                    std::strcmp(k2, key) == 0 && (t == 8 || t == 16 || t == 32 || t == 64) &&
+                int t = 0, td = 0, c = 0, o = 0;
+                auto tile_ok = [](int v) { return v == 8 || v == 16 || v == 32 || v == 64; };
+                if (std::sscanf(line, "%639s %d %d %d %d", k2, &t, &td, &c, &o) == 5 &&
+                    std::strcmp(k2, key) == 0 && tile_ok(t) && tile_ok(td) &&
                     (c == 128 || c == 256 || c == 512) && (o == 0 || o == 1)) {
                     pl->tile = t;
+                    pl->tile_d = td;
                     pl->lds_cap = c;
                     pl->order = o;
                     hit = true;
@@ -811,8 +838,9 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
     hipEvent_t e0 = nullptr, e1 = nullptr;
     r = hip_check(hipEventCreate(&e0), "event");
     if (!r) r = hip_check(hipEventCreate(&e1), "event");
-    auto time_one = [&](int tile, int cap, int order, float& best_ms) -> int {
+    auto time_one = [&](int tile, int tile_d, int cap, int order, float& best_ms) -> int {
         pl->tile = tile;
+        pl->tile_d = tile_d;
         pl->lds_cap = cap;
         pl->order = order;
         float ms = 3.0e38f;
@@ -833,38 +861,46 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
         best_ms = ms;
         return SWSPH_OK;
     };
-    // coordinate descent: tile size, then LDS capacity, then task order
-    int bt = pl->tile, bc = pl->lds_cap, bo = pl->order;
+    // coordinate descent: gradient/force tile size, density tile size, LDS
+    // capacity, task order
+    int bt = pl->tile, btd = pl->tile_d, bc = pl->lds_cap, bo = pl->order;
     float best = 3.0e38f;
-    if (!r) r = time_one(bt, bc, bo, best);
+    if (!r) r = time_one(bt, btd, bc, bo, best);
     const int tiles[4] = {8, 16, 32, 64}, caps[3] = {128, 256, 512}, orders[2] = {0, 1};
     for (int k = 0; k < 4 && !r; ++k) {
         if (tiles[k] == bt) continue;
         float t = 0.f;
-        r = time_one(tiles[k], bc, bo, t);
+        r = time_one(tiles[k], btd, bc, bo, t);
         if (!r && t < best) { best = t; bt = tiles[k]; }
+    }
+    for (int k = 0; k < 4 && !r; ++k) {
+        if (tiles[k] == btd) continue;
+        float t = 0.f;
+        r = time_one(bt, tiles[k], bc, bo, t);
+        if (!r && t < best) { best = t; btd = tiles[k]; }
     }
     for (int k = 0; k < 3 && !r; ++k) {
         if (caps[k] == bc) continue;
         float t = 0.f;
-        r = time_one(bt, caps[k], bo, t);
+        r = time_one(bt, btd, caps[k], bo, t);
         if (!r && t < best) { best = t; bc = caps[k]; }
     }
     for (int k = 0; k < 2 && !r; ++k) {
         if (orders[k] == bo) continue;
         float t = 0.f;
-        r = time_one(bt, bc, orders[k], t);
+        r = time_one(bt, btd, bc, orders[k], t);
         if (!r && t < best) { best = t; bo = orders[k]; }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     pl->tile = bt;
+    pl->tile_d = btd;
     pl->lds_cap = bc;
     pl->order = bo;
     if (r) return r;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d\n", key, bt, bc, bo);
+            std::fprintf(f, "%s %d %d %d %d\n", key, bt, btd, bc, bo);
             std::fclose(f);
         }
     }

@@ -22,6 +22,14 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+__global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+void launch_copy_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, dst, src);
+}
+
 void launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return;
     int64_t blocks = (n + 255) / 256;
@@ -293,8 +301,9 @@ template void launch_gather<double>(const swsph_particles*, const BoxInfo*, cons
 // compact and their task lists short even where the particle density
 // changes by orders of magnitude; they come out in Morton order per box.
 // Built in three passes: flag the first particle of every tile, scan the
-// flags (tile index), write the tiles.  The tile count stays on the device
-// (Counters::n_tiles); kernels over tiles loop up to it.
+// flags (tile index), write the tiles.  The tile count stays on the device;
+// kernels over tiles loop up to it.  The density loop may use its own tile
+// size.
 
 // Sorted range [cbeg, cend) of the tile cell of binned particle s.
 __device__ __forceinline__ void tile_cell(int64_t s, const BoxInfo& bi, uint32_t mort,
@@ -327,10 +336,10 @@ __global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict_
                             const uint32_t* __restrict__ keys, const int32_t* __restrict__ perm,
                             const int32_t* __restrict__ cstart, int32_t tile,
                             const int32_t* __restrict__ flag, const int32_t* __restrict__ tidx,
-                            Tile* __restrict__ tiles, Counters* __restrict__ cnt) {
+                            Tile* __restrict__ tiles, unsigned long long* __restrict__ ntiles) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
-    if (s == n - 1) cnt->n_tiles = (unsigned long long)tidx[n];
+    if (s == n - 1) *ntiles = (unsigned long long)tidx[n];
     if (!flag[s]) return;
     const int b = box_of_sorted(s, n_box, boxtab);
     const BoxInfo bi = boxtab[b];
@@ -350,8 +359,8 @@ __global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict_
 template <typename T>
 __global__ void k_tile_bounds(const V4<T>* __restrict__ pos4, const T* __restrict__ hs,
                               Tile* __restrict__ tiles, int32_t* __restrict__ order,
-                              const Counters* __restrict__ cnt) {
-    const int64_t nt = (int64_t)cnt->n_tiles;
+                              const unsigned long long* __restrict__ ntiles) {
+    const int64_t nt = (int64_t)*ntiles;
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; t < nt;
@@ -389,16 +398,25 @@ unsigned wave_grid(int64_t items, int wpb) {
 }
 
 template <typename T>
-void launch_make_tiles(const BinPtrs& b, hipStream_t s) {
-    if (b.n <= 0) return;
+static void make_tile_set(const BinPtrs& b, int32_t tile, Tile* tiles, int32_t* order,
+                          unsigned long long* ntiles, hipStream_t s) {
     const unsigned g = (unsigned)((b.n + 255) / 256);
     hipLaunchKernelGGL(k_tile_flags, dim3(g), dim3(256), 0, s, b.n, b.n_box, b.boxtab, b.keys,
-                       b.perm, b.cstart, b.tile, b.slot);
+                       b.perm, b.cstart, tile, b.slot);
     launch_exclusive_scan(b.slot, b.n, b.scan_part, b.tmpidx, s);
     hipLaunchKernelGGL(k_tile_make, dim3(g), dim3(256), 0, s, b.n, b.n_box, b.boxtab, b.keys,
-                       b.perm, b.cstart, b.tile, b.slot, b.tmpidx, b.tiles, b.cnt);
+                       b.perm, b.cstart, tile, b.slot, b.tmpidx, tiles, ntiles);
     hipLaunchKernelGGL(k_tile_bounds<T>, dim3(wave_grid(b.tile_cap, 4)), dim3(4 * WAVE), 0, s,
-                       (const V4<T>*)b.pos4, (const T*)b.hs, b.tiles, b.order, b.cnt);
+                       (const V4<T>*)b.pos4, (const T*)b.hs, tiles, order,
+                       (const unsigned long long*)ntiles);
+}
+
+template <typename T>
+void launch_make_tiles(const BinPtrs& b, hipStream_t s) {
+    if (b.n <= 0) return;
+    make_tile_set<T>(b, b.tile, b.tiles, b.order, &b.cnt->n_tiles, s);
+    if (b.tiles_d != b.tiles) make_tile_set<T>(b, b.tile_d, b.tiles_d, b.order_d, &b.cnt->n_tiles_d, s);
+    else launch_copy_u64(&b.cnt->n_tiles_d, &b.cnt->n_tiles, s);
 }
 template void launch_make_tiles<float>(const BinPtrs&, hipStream_t);
 template void launch_make_tiles<double>(const BinPtrs&, hipStream_t);

@@ -31,8 +31,11 @@ struct BinPtrs {
     int32_t *fine_count, *cstart, *scan_part;
     void *pos4, *vel4, *hs, *dens4;
     float* hmaxpyr;
-    Tile* tiles;
+    Tile* tiles;               // the tile set of the loop at hand
     int32_t* order;
+    unsigned long long* ntiles;  // its device count
+    Tile* tiles_d;             // density tiles (may alias tiles)
+    int32_t* order_d;
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *leaf_cnt, *leaf_off, *leaf_part;
     int2* leaves;
@@ -43,7 +46,8 @@ struct BinPtrs {
     int32_t *d_int, *f_int;
     int64_t n;
     int32_t n_box;
-    int32_t tile;      // most particles per tile
+    int32_t tile;      // most particles per tile (gradient/force)
+    int32_t tile_d;    // most particles per density tile
     int64_t tile_cap;  // most tiles (the device holds the count: cnt->n_tiles)
     int64_t n_fine, n_pyr;
 };
@@ -52,6 +56,9 @@ struct BinPtrs {
 enum Mode { MODE_QUEUE = 0, MODE_FLAT = 1, MODE_PER_TASK = 2 };
 
 void launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
+void launch_copy_u64(unsigned long long* dst, const unsigned long long* src, hipStream_t s);
+struct BinPtrs;
+BinPtrs density_view(const BinPtrs& b);
 template <typename T>
 void launch_keys(const swsph_particles* p, const BoxInfo* boxtab, uint32_t* keys,
                  int32_t* slot, int32_t* fine_count, Counters* cnt, hipStream_t s);

@@ -155,8 +155,12 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
         if (cached) {
             sweep(ns);
         } else {
+            // re-staging: only the supports of this sweep's h are needed
+            // (the bounding-box distance never exceeds a lane's distance)
+            const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
+            const T Rs = Hs < R ? Hs : R;
             int fl = 0;
-            ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, fl, sweep);
+            ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, Rs * Rs, fl, sweep);
             sweep(ns);
         }
     }
@@ -440,9 +444,10 @@ static int launch_loop(KArgs<T> a, int mode, int lds_cap, int queue_slot, hipStr
 
 // Indices of the tiles flagged for a density fix-up (any order: tiles are
 // independent), one atomic per wavefront.
-__global__ void k_fix_list(const int32_t* __restrict__ tflag, Counters* __restrict__ cnt,
-                           int32_t* __restrict__ list) {
-    const int64_t nt = (int64_t)cnt->n_tiles;
+__global__ void k_fix_list(const int32_t* __restrict__ tflag,
+                           const unsigned long long* __restrict__ ntiles,
+                           Counters* __restrict__ cnt, int32_t* __restrict__ list) {
+    const int64_t nt = (int64_t)*ntiles;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nt; base += nth) {
         const int64_t t = base + threadIdx.x;
@@ -459,7 +464,8 @@ __global__ void k_fix_list(const int32_t* __restrict__ tflag, Counters* __restri
 // Density: the first pass, then up to three fix-up passes for tiles whose
 // Newton iteration needed a wider task list (the last one latches failures).
 template <typename T>
-int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
+int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
+    const BinPtrs b = density_view(bin);
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.d_out;
     a.iout = b.d_int;
@@ -475,7 +481,8 @@ int launch_density(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hi
     for (int pass = 1; pass <= 3 && !r; ++pass) {
         launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
         hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
-                           (const int32_t*)b.tflag, b.cnt, b.tmpidx);
+                           (const int32_t*)b.tflag, (const unsigned long long*)b.ntiles, b.cnt,
+                           b.tmpidx);
         launch_tasks<T>(b, sc, 0, true, s);
         a.fixup = pass == 3 ? 2 : 1;
         timer_begin(sc.timer, 0, s);

@@ -290,7 +290,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
     a.order = b.order;
-    a.ntask = &b.cnt->n_tiles;
+    a.ntask = b.ntiles;
     a.tile_cap = b.tile_cap;
     a.task = 0;
     a.leaf_cnt = b.leaf_cnt;

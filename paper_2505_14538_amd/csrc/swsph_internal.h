@@ -56,9 +56,10 @@ struct Counters {
     unsigned long long restages;
     unsigned long long queue[4][8];    // task-queue heads per loop (8: one per XCD segment)
     unsigned long long leaf_need;      // leaves requested by the last task build
-    unsigned long long n_tiles;        // tiles made by the last bin
+    unsigned long long n_tiles;        // tiles of the gradient/force (and adjoint) loops
+    unsigned long long n_tiles_d;      // tiles of the density loop
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
-    unsigned long long reserved[7];
+    unsigned long long reserved[6];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };
@@ -69,7 +70,7 @@ struct Layout {
     uint64_t keys, slot, tmpidx, perm, rank;  // slot/tmpidx: reused for the tile scan
     uint64_t fine_count, cstart, scan_part;
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
-    uint64_t tiles, order, ord_table, ord_base;
+    uint64_t tiles, order, tiles_d, order_d, ord_table, ord_base;
     // task lists (CSR of cells per tile) and density fix-up state
     uint64_t leaf_cnt, leaf_off, leaf_part, leaves, trad, tflag;
     // sorted-order results

@@ -18,6 +18,7 @@ template <typename T>
 struct TArgs {
     const BoxInfo* boxtab;
     Tile* tiles;
+    const unsigned long long* ntiles;
     int64_t tile_cap;
     const int32_t* cstart;
     const float* hpyr;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int pass,
     const int wave = threadIdx.x / WAVE;
     SearchMem& m = smem_search[wave];
     const int lane = lane_id();
-    const int64_t nt = (int64_t)a.cnt->n_tiles;
+    const int64_t nt = (int64_t)*a.ntiles;
     if (pass == 0) {
         const int64_t nth = (int64_t)gridDim.x * blockDim.x;
         for (int64_t t = nt + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.tile_cap;
@@ -176,24 +177,24 @@ __device__ __forceinline__ void block_class_counts(const Tile* __restrict__ tile
 }
 
 __global__ void __launch_bounds__(ORD_T) k_order_hist(const Tile* __restrict__ tiles,
-                                                      const Counters* __restrict__ cnt,
+                                                      const unsigned long long* __restrict__ ntiles,
                                                       int32_t nblk, int32_t* __restrict__ table) {
     __shared__ int32_t hist[ORD_B][ORD_T];
     __shared__ int32_t tot[ORD_B];
-    const int64_t nt = (int64_t)cnt->n_tiles;
+    const int64_t nt = (int64_t)*ntiles;
     int64_t lo, hi;
     block_class_counts(tiles, nt, hist, tot, lo, hi);
     if (threadIdx.x < ORD_B) table[(int64_t)threadIdx.x * nblk + blockIdx.x] = tot[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(ORD_T) k_order_scatter(const Tile* __restrict__ tiles,
-                                                         const Counters* __restrict__ cnt,
+                                                         const unsigned long long* __restrict__ ntiles,
                                                          int32_t nblk,
                                                          const int32_t* __restrict__ base,
                                                          int32_t* __restrict__ order) {
     __shared__ int32_t hist[ORD_B][ORD_T];
     __shared__ int32_t tot[ORD_B];
-    const int64_t nt = (int64_t)cnt->n_tiles;
+    const int64_t nt = (int64_t)*ntiles;
     int64_t lo, hi;
     block_class_counts(tiles, nt, hist, tot, lo, hi);
     const int k = threadIdx.x;
@@ -211,10 +212,11 @@ void launch_order(const BinPtrs& b, hipStream_t s) {
     const int32_t nblk = (int32_t)((b.tile_cap + ORD_CHUNK - 1) / ORD_CHUNK);
     const int64_t nent = (int64_t)ORD_B * nblk;
     hipLaunchKernelGGL(k_order_hist, dim3(nblk), dim3(ORD_T), 0, s, (const Tile*)b.tiles,
-                       (const Counters*)b.cnt, nblk, b.ord_table);
+                       (const unsigned long long*)b.ntiles, nblk, b.ord_table);
     launch_exclusive_scan(b.ord_table, nent, b.scan_part, b.ord_base, s);
     hipLaunchKernelGGL(k_order_scatter, dim3(nblk), dim3(ORD_T), 0, s, (const Tile*)b.tiles,
-                       (const Counters*)b.cnt, nblk, (const int32_t*)b.ord_base, b.order);
+                       (const unsigned long long*)b.ntiles, nblk, (const int32_t*)b.ord_base,
+                       b.order);
 }
 
 template <typename T>
@@ -222,6 +224,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     TArgs<T> a;
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
+    a.ntiles = b.ntiles;
     a.tile_cap = b.tile_cap;
     a.cstart = b.cstart;
     a.hpyr = b.hmaxpyr;

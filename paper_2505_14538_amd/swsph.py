@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
                 ("h_max_iter", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32),
                 ("lds_cap", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("leaf_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("leaf_max", ctypes.c_int32), ("tile_dens", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -85,14 +86,15 @@ class Stats(ctypes.Structure):
                 ("pairs_tested", ctypes.c_uint64 * 4), ("pairs_inside", ctypes.c_uint64 * 4),
                 ("newton_sweeps", ctypes.c_uint64), ("newton_max", ctypes.c_uint32),
                 ("newton_failed", ctypes.c_uint32), ("leaves", ctypes.c_uint64),
-                ("restages", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 6)]
+                ("restages", ctypes.c_uint64), ("n_tiles_dens", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 5)]
 
     def as_dict(self) -> Dict:
         return {"status": self.status, "n_tiles": self.n_tiles,
                 "pairs_tested": list(self.pairs_tested), "pairs_inside": list(self.pairs_inside),
                 "newton_sweeps": self.newton_sweeps, "newton_max": self.newton_max,
                 "newton_failed": self.newton_failed, "leaves": self.leaves,
-                "restages": self.restages}
+                "restages": self.restages, "n_tiles_dens": self.n_tiles_dens}
 
 
 _vp = ctypes.c_void_p
@@ -116,7 +118,7 @@ _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut)
 _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
 _lib.swsph_autotune.argtypes = [_vp, _P(ParticlesC), _vp, _vp, ctypes.c_char_p]
 _lib.swsph_plan_get_tuning.argtypes = [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
-                                       _P(ctypes.c_int32), _P(ctypes.c_int32)]
+                                       _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]
 _lib.swsph_kernel_times.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_uint64), _vp]
 _lib.swsph_reset_timers.argtypes = [_vp]
 
@@ -390,10 +392,11 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        a, b, c, d = (ctypes.c_int32() for _ in range(4))
+        a, b, c, d, e = (ctypes.c_int32() for _ in range(5))
         _check(_lib.swsph_plan_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b),
-                                          ctypes.byref(c), ctypes.byref(d)))
-        return {"tile": a.value, "lds_cap": b.value, "order": c.value, "leaf_max": d.value}
+                                          ctypes.byref(c), ctypes.byref(d), ctypes.byref(e)))
+        return {"tile": a.value, "tile_dens": e.value, "lds_cap": b.value, "order": c.value,
+                "leaf_max": d.value}
 
 
 def host(d: Dict[str, object]) -> Dict[str, np.ndarray]:

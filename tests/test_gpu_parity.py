@@ -56,7 +56,7 @@ def of_max(a, b):
 
 # ----------------------------------------------------------------- tiny
 
-@pytest.mark.parametrize("tile", [64, 32, 16])
+@pytest.mark.parametrize("tile", [64, 32, 16, 8])
 def test_tiny_fp32_parity(S, oracle_mod, tile):
     O = oracle_mod
     p = W.tiny()
@@ -64,7 +64,7 @@ def test_tiny_fp32_parity(S, oracle_mod, tile):
     od = O.density(p, O.Params())
     og = O.gradient(p, od)
     of = O.force(p, od)
-    d, g, f, st, _ = run_all(S, p, tile=tile)
+    d, g, f, st, _ = run_all(S, p, tile=tile, tile_dens=tile)
     assert st["code"] == 0, st
     assert rel(d["h"], od["h"]).max() < 1e-5
     assert rel(d["rho"], od["rho"]).max() < 1e-5
@@ -205,7 +205,8 @@ def test_autotune_keeps_results(S, oracle_mod, tmp_path):
     dp = S.to_device(p)
     cache = str(tmp_path / "tune.txt")
     t = plan.autotune(dp, cache)
-    assert t["tile"] in (8, 16, 32, 64) and t["lds_cap"] in (128, 256, 512) and t["order"] in (0, 1)
+    assert t["tile"] in (8, 16, 32, 64) and t["tile_dens"] in (8, 16, 32, 64)
+    assert t["lds_cap"] in (128, 256, 512) and t["order"] in (0, 1)
     # a second plan reads the choice from the cache
     plan2 = S.Plan()
     assert plan2.autotune(dp, cache) == t

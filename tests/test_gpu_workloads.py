@@ -106,8 +106,8 @@ def test_ragged_small_and_tiles(S, oracle_mod):
     """A set whose size is no multiple of any tile, for every tile size."""
     O = oracle_mod
     p = W.tiny(nside=11)
-    for tile in (16, 32, 64):
-        d, g, f, st = gpu_all(S, p, tile=tile)
+    for tile in (8, 16, 32, 64):
+        d, g, f, st = gpu_all(S, p, tile=tile, tile_dens=tile)
         assert st["code"] == 0, st
         check_sample(O, p, d, g, f, np.arange(p.n))
 
