@@ -110,7 +110,8 @@ typedef struct swsph_config {
                             segment per XCD (default) */
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: auto) */
     int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 8) */
-    int32_t reserved[4];
+    int32_t lds_cap_dens; /* staged j-particles per wavefront, density loop (0: 256) */
+    int32_t reserved[3];
 } swsph_config;
 
 /* Particle set.  Positions must lie in [0, box_size[b]) of their box b.
@@ -268,8 +269,11 @@ int swsph_kernel_times(swsph_plan* plan, double ms[4], uint64_t launches[4], voi
 int swsph_reset_timers(swsph_plan* plan);
 
 /* The tuning the plan will use: tile, lds_cap, order, leaf_max. */
-int swsph_plan_get_tuning(const swsph_plan* plan, int32_t* tile, int32_t* lds_cap,
-                          int32_t* order, int32_t* leaf_max, int32_t* tile_dens);
+/* The execution options in effect (after defaults or swsph_autotune). */
+typedef struct swsph_tuning {
+    int32_t tile, tile_dens, lds_cap, lds_cap_dens, order, leaf_max;
+} swsph_tuning;
+int swsph_plan_get_tuning(const swsph_plan* plan, swsph_tuning* out);
 
 #ifdef __cplusplus
 }

@@ -54,9 +54,11 @@ constexpr int KMAX = 10;               // Morton key: 3 x 10 bits per box
 constexpr int64_t FINE_MAX = int64_t(1) << 29;
 
 // Task-list capacity: 48 cells per particle (cell tiles of <= 64 particles
-// need ~2-8 on clustered and uniform sets).  Overflow latches
-// SWSPH_ST_CAPACITY.
-int64_t leaf_capacity(int64_t n) { return 48 * n + 4096; }
+// need ~2-8 on clustered and uniform sets), below 2^31 (int32 offsets).
+// Overflow latches SWSPH_ST_CAPACITY.
+int64_t leaf_capacity(int64_t n) {
+    return std::min<int64_t>(48 * n + 4096, (int64_t(1) << 31) - 1);
+}
 
 int choose_k(int64_t nb) {
     // finest grid with about one cell per particle or more (8^k <= 8 nb)
@@ -138,7 +140,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.leaf_cnt = take(4 * (uint64_t)(toff + 1));
     l.leaf_off = take(4 * (uint64_t)(toff + 2));
-    l.leaf_part = take(4 * (uint64_t)scan_partials_needed(toff + 1));
+    l.ovf = take(4 * (uint64_t)toff);
     G.leaf_cap = leaf_capacity(n);
     l.leaves = take(8 * (uint64_t)G.leaf_cap);
     l.trad = take(4 * (uint64_t)toff);
@@ -199,7 +201,7 @@ void swsph::timer_end(Timer* t, int loop, hipStream_t s) {
 struct swsph_plan {
     swsph_config cfg;
     swsph::Timer* timer = nullptr;
-    int32_t tile, tile_d, lds_cap, order, leaf_max;
+    int32_t tile, tile_d, lds_cap, lds_cap_d, order, leaf_max;
     bool binned = false;
     void* ws = nullptr;
     Geometry G;
@@ -227,6 +229,9 @@ int check_config(const swsph_config* c) {
         return fail(SWSPH_E_ARG, "tile_dens must be 0, 8, 16, 32 or 64");
     if (c->lds_cap != 0 && c->lds_cap != 128 && c->lds_cap != 256 && c->lds_cap != 512)
         return fail(SWSPH_E_ARG, "lds_cap must be 0, 128, 256 or 512");
+    if (c->lds_cap_dens != 0 && c->lds_cap_dens != 128 && c->lds_cap_dens != 256 &&
+        c->lds_cap_dens != 512)
+        return fail(SWSPH_E_ARG, "lds_cap_dens must be 0, 128, 256 or 512");
     if (c->order != 0 && c->order != 1) return fail(SWSPH_E_ARG, "order must be 0 or 1");
     if (c->leaf_max < 0 || c->leaf_max > 4096) return fail(SWSPH_E_ARG, "leaf_max in [0, 4096]");
     if ((c->flags & SWSPH_PER_TASK_LAUNCH) && (c->flags & SWSPH_FLAT_LAUNCH))
@@ -297,7 +302,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.ord_base = (int32_t*)(w + l.ord_base);
     b.leaf_cnt = (int32_t*)(w + l.leaf_cnt);
     b.leaf_off = (int32_t*)(w + l.leaf_off);
-    b.leaf_part = (int32_t*)(w + l.leaf_part);
+    b.ovf = (int32_t*)(w + l.ovf);
     b.leaves = (int2*)(w + l.leaves);
     b.leaf_cap = pl->G.leaf_cap;
     b.trad = (float*)(w + l.trad);
@@ -381,6 +386,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     pl->tile = cfg->tile ? cfg->tile : 64;
     pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 8;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
+    pl->lds_cap_d = cfg->lds_cap_dens ? cfg->lds_cap_dens : 256;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 32;
     if (cfg->flags & SWSPH_TIMING) pl->timer = new (std::nothrow) swsph::Timer();
@@ -398,14 +404,14 @@ int swsph_plan_destroy(swsph_plan* pl) {
     return SWSPH_OK;
 }
 
-int swsph_plan_get_tuning(const swsph_plan* pl, int32_t* tile, int32_t* lds_cap, int32_t* order,
-                          int32_t* leaf_max, int32_t* tile_dens) {
-    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
-    if (tile) *tile = pl->tile;
-    if (tile_dens) *tile_dens = pl->tile_d;
-    if (lds_cap) *lds_cap = pl->lds_cap;
-    if (order) *order = pl->order;
-    if (leaf_max) *leaf_max = pl->leaf_max;
+int swsph_plan_get_tuning(const swsph_plan* pl, swsph_tuning* out) {
+    if (!pl || !out) return fail(SWSPH_E_ARG, "plan and out are required");
+    out->tile = pl->tile;
+    out->tile_dens = pl->tile_d;
+    out->lds_cap = pl->lds_cap;
+    out->lds_cap_dens = pl->lds_cap_d;
+    out->order = pl->order;
+    out->leaf_max = pl->leaf_max;
     return SWSPH_OK;
 }
 
@@ -500,10 +506,10 @@ int swsph_density(swsph_plan* pl, const swsph_particles* p, swsph_density_out* o
     Scheme sc = scheme_of(pl);
     const int mode = mode_of(pl);
     if (pl->cfg.dtype == SWSPH_F64) {
-        r = launch_density<double>(b, sc, mode, pl->lds_cap, s);
+        r = launch_density<double>(b, sc, mode, pl->lds_cap_d, s);
         unsort_density<double>(b, o, s);
     } else {
-        r = launch_density<float>(b, sc, mode, pl->lds_cap, s);
+        r = launch_density<float>(b, sc, mode, pl->lds_cap_d, s);
         unsort_density<float>(b, o, s);
     }
     if (r) return fail(SWSPH_E_HIP, "density kernel launch failed");
@@ -675,6 +681,7 @@ std::vector<uint64_t> step_key(const swsph_plan* pl, const swsph_particles* p,
     k.push_back((uint64_t)pl->tile);
     k.push_back((uint64_t)pl->tile_d);
     k.push_back((uint64_t)pl->lds_cap);
+    k.push_back((uint64_t)pl->lds_cap_d);
     k.push_back((uint64_t)pl->order);
     k.push_back((uint64_t)pl->leaf_max);
     return k;
@@ -807,14 +814,16 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
             bool hit = false;
             while (std::fgets(line, sizeof line, f)) {
                 char k2[640];
-                int t = 0, td = 0, c = 0, o = 0;
+                int t = 0, td = 0, c = 0, cd = 0, o = 0;
                 auto tile_ok = [](int v) { return v == 8 || v == 16 || v == 32 || v == 64; };
-                if (std::sscanf(line, "%639s %d %d %d %d", k2, &t, &td, &c, &o) == 5 &&
-                    std::strcmp(k2, key) == 0 && tile_ok(t) && tile_ok(td) &&
-                    (c == 128 || c == 256 || c == 512) && (o == 0 || o == 1)) {
+                auto cap_ok = [](int v) { return v == 128 || v == 256 || v == 512; };
+                if (std::sscanf(line, "%639s %d %d %d %d %d", k2, &t, &td, &c, &cd, &o) == 6 &&
+                    std::strcmp(k2, key) == 0 && tile_ok(t) && tile_ok(td) && cap_ok(c) &&
+                    cap_ok(cd) && (o == 0 || o == 1)) {
                     pl->tile = t;
                     pl->tile_d = td;
                     pl->lds_cap = c;
+                    pl->lds_cap_d = cd;
                     pl->order = o;
                     hit = true;
                 }
@@ -838,10 +847,12 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
     hipEvent_t e0 = nullptr, e1 = nullptr;
     r = hip_check(hipEventCreate(&e0), "event");
     if (!r) r = hip_check(hipEventCreate(&e1), "event");
-    auto time_one = [&](int tile, int tile_d, int cap, int order, float& best_ms) -> int {
+    auto time_one = [&](int tile, int tile_d, int cap, int cap_d, int order,
+                        float& best_ms) -> int {
         pl->tile = tile;
         pl->tile_d = tile_d;
         pl->lds_cap = cap;
+        pl->lds_cap_d = cap_d;
         pl->order = order;
         float ms = 3.0e38f;
         for (int rep = 0; rep < 2; ++rep) {
@@ -861,46 +872,38 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
         best_ms = ms;
         return SWSPH_OK;
     };
-    // coordinate descent: gradient/force tile size, density tile size, LDS
-    // capacity, task order
-    int bt = pl->tile, btd = pl->tile_d, bc = pl->lds_cap, bo = pl->order;
+    // coordinate descent over the options: gradient/force tile size, density
+    // tile size, LDS capacities (gradient/force, density), task order
+    int v[5] = {pl->tile, pl->tile_d, pl->lds_cap, pl->lds_cap_d, pl->order};
     float best = 3.0e38f;
-    if (!r) r = time_one(bt, btd, bc, bo, best);
+    if (!r) r = time_one(v[0], v[1], v[2], v[3], v[4], best);
     const int tiles[4] = {8, 16, 32, 64}, caps[3] = {128, 256, 512}, orders[2] = {0, 1};
-    for (int k = 0; k < 4 && !r; ++k) {
-        if (tiles[k] == bt) continue;
-        float t = 0.f;
-        r = time_one(tiles[k], btd, bc, bo, t);
-        if (!r && t < best) { best = t; bt = tiles[k]; }
-    }
-    for (int k = 0; k < 4 && !r; ++k) {
-        if (tiles[k] == btd) continue;
-        float t = 0.f;
-        r = time_one(bt, tiles[k], bc, bo, t);
-        if (!r && t < best) { best = t; btd = tiles[k]; }
-    }
-    for (int k = 0; k < 3 && !r; ++k) {
-        if (caps[k] == bc) continue;
-        float t = 0.f;
-        r = time_one(bt, btd, caps[k], bo, t);
-        if (!r && t < best) { best = t; bc = caps[k]; }
-    }
-    for (int k = 0; k < 2 && !r; ++k) {
-        if (orders[k] == bo) continue;
-        float t = 0.f;
-        r = time_one(bt, btd, bc, orders[k], t);
-        if (!r && t < best) { best = t; bo = orders[k]; }
+    const int* cand[5] = {tiles, tiles, caps, caps, orders};
+    const int ncand[5] = {4, 4, 3, 3, 2};
+    for (int d = 0; d < 5 && !r; ++d) {
+        for (int k = 0; k < ncand[d] && !r; ++k) {
+            if (cand[d][k] == v[d]) continue;
+            int w[5] = {v[0], v[1], v[2], v[3], v[4]};
+            w[d] = cand[d][k];
+            float t = 0.f;
+            r = time_one(w[0], w[1], w[2], w[3], w[4], t);
+            if (!r && t < best) {
+                best = t;
+                v[d] = w[d];
+            }
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    pl->tile = bt;
-    pl->tile_d = btd;
-    pl->lds_cap = bc;
-    pl->order = bo;
+    pl->tile = v[0];
+    pl->tile_d = v[1];
+    pl->lds_cap = v[2];
+    pl->lds_cap_d = v[3];
+    pl->order = v[4];
     if (r) return r;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d\n", key, bt, btd, bc, bo);
+            std::fprintf(f, "%s %d %d %d %d %d\n", key, v[0], v[1], v[2], v[3], v[4]);
             std::fclose(f);
         }
     }

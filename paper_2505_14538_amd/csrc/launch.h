@@ -37,7 +37,8 @@ struct BinPtrs {
     Tile* tiles_d;             // density tiles (may alias tiles)
     int32_t* order_d;
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
-    int32_t *leaf_cnt, *leaf_off, *leaf_part;
+    int32_t *leaf_cnt, *leaf_off;
+    int32_t* ovf;
     int2* leaves;
     int64_t leaf_cap;
     float* trad;

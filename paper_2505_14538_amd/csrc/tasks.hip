@@ -24,28 +24,44 @@ struct TArgs {
     const float* hpyr;
     const T* hs;
     int32_t* leaf_cnt;
-    const int32_t* leaf_off;
+    int32_t* leaf_off;
     int2* leaves;
     int64_t leaf_cap;
     float* trad;
     const int32_t* tflag;
+    int32_t* ovf;               // tiles whose list overflowed the LDS buffer
     Counters* cnt;
     T eps;
     T margin;
     int32_t leaf_max;
 };
 
-// Task list of tile t (count pass: size, radius and cost; fill pass: the
-// leaves).  Wavefront-uniform.
+// Task list of tile t from one cell search.  Main pass: the tile's leaves
+// are gathered in LDS (up to TASK_BUF) and copied to space taken from a
+// device bump counter, so each tile's list is contiguous; its radius and
+// cost are recorded.  A tile with more leaves only counts them and is put
+// on the overflow list; the overflow pass takes exactly that much space and
+// runs its search again, writing straight to global memory.
+// Wavefront-uniform.
+#ifndef SWSPH_TASK_BUF
+#define SWSPH_TASK_BUF 512
+#endif
+constexpr int TASK_BUF = SWSPH_TASK_BUF;  // leaves buffered in LDS per wavefront
+
+struct TaskMem {
+    SearchMem sm;
+    int2 buf[TASK_BUF];
+};
+
 template <typename T, int MODE>
-__device__ void task_one(const TArgs<T>& a, SearchMem& m, const Tile& tl, int64_t t, int pass,
-                         int fixup) {
+__device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t,
+                         bool overflow_pass, int fixup, int64_t base) {
     const int lane = lane_id();
     const BoxInfo bi = a.boxtab[tl.box];
     const float L = (float)bi.L;
     const float Rcap = 0.5f * L * (1.0f - 1e-6f);
     float R;
-    if (pass == 1 || (MODE == 0 && fixup)) {
+    if (overflow_pass || (MODE == 0 && fixup)) {
         R = a.trad[t];
     } else {
         const bool act = lane < tl.count;
@@ -66,74 +82,114 @@ __device__ void task_one(const TArgs<T>& a, SearchMem& m, const Tile& tl, int64_
     float Rstart = R;
     if (MODE == 2) Rstart = fmaxf(R, a.hpyr[bi.pyr_off]);
     SearchState st;
-    search_init(m, st, bi, g, Rstart);
+    search_init(m.sm, st, bi, g, Rstart);
     const float R2 = R * R;
     int64_t total = 0, cand = 0;
-    const int64_t base = pass == 1 ? (int64_t)a.leaf_off[t] : 0;
-    const int64_t mine = pass == 1 ? (int64_t)a.leaf_cnt[t] : 0;
+    const int64_t mine = overflow_pass ? (int64_t)a.leaf_cnt[t] : 0;
     for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
-        const bool done = search_step<MODE == 2>(m, st, bi, g, R2, a.cstart, a.hpyr, a.leaf_max,
-                                                 a.cnt);
+        const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr,
+                                                 a.leaf_max, a.cnt);
         if (st.nleaf > 0) {
-            if (pass == 1) {
-                for (int k = lane; k < st.nleaf; k += WAVE) {
-                    const int64_t at = total + k;
-                    if (at < mine && base + at < a.leaf_cap)
-                        a.leaves[base + at] = pack_leaf(m.lbeg[k], m.lcnt[k], m.lshift[k]);
+            int c = 0;
+            for (int k = lane; k < st.nleaf; k += WAVE) {
+                const int64_t at = total + k;
+                const int2 v = pack_leaf(m.sm.lbeg[k], m.sm.lcnt[k], m.sm.lshift[k]);
+                if (overflow_pass) {
+                    if (at < mine && base + at < a.leaf_cap) a.leaves[base + at] = v;
+                } else if (at < TASK_BUF) {
+                    m.buf[at] = v;
                 }
-            } else {
-                int c = 0;
-                for (int k = lane; k < st.nleaf; k += WAVE) c += m.lcnt[k];
-                cand += wave_sum(c);
+                c += m.sm.lcnt[k];
             }
+            cand += wave_sum(c);
             total += st.nleaf;
             st.nleaf = 0;
             wave_sync();
         }
         if (done) break;
     }
-    if (lane == 0) {
-        if (pass == 0) {
+    if (!overflow_pass) {
+        int64_t at = 0;
+        if (lane == 0) {
             a.leaf_cnt[t] = (int32_t)total;
             a.tiles[t].cost = (float)tl.count * (float)cand;
             atomicAdd(&a.cnt->leaves, (unsigned long long)total);
-        } else if (base + total > a.leaf_cap) {
-            latch(a.cnt, SWSPH_ST_CAPACITY);
+            if (total > TASK_BUF) {
+                a.leaf_off[t] = -1;
+                a.ovf[atomicAdd(&a.cnt->n_ovf, 1ull)] = (int32_t)t;
+            } else {
+                at = (int64_t)atomicAdd(&a.cnt->leaf_used, (unsigned long long)total);
+                a.leaf_off[t] = at + total <= a.leaf_cap ? (int32_t)at : -1;
+                if (at + total > a.leaf_cap) {
+                    a.leaf_cnt[t] = 0;
+                    latch(a.cnt, SWSPH_ST_CAPACITY);
+                }
+            }
         }
+        at = __shfl(at, 0, WAVE);
+        if (total <= TASK_BUF && at + total <= a.leaf_cap)
+            for (int k = lane; k < total; k += WAVE) a.leaves[at + k] = m.buf[k];
+    } else if (lane == 0 && base + total > a.leaf_cap) {
+        latch(a.cnt, SWSPH_ST_CAPACITY);
     }
     wave_sync();
 }
 
 // MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
 // 2 force (eps*hmax, and cells whose own support reaches the tile).
-// One wavefront per tile, grid-stride over the device tile count; the count
-// pass also zeroes the counts of the unused tile slots (the scan runs over
-// all of them).
+// One wavefront per tile, grid-stride over the device tile count.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int pass, int fixup) {
-    __shared__ SearchMem smem_search[TASK_WPB];
+__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup) {
+    __shared__ TaskMem smem_task[TASK_WPB];
     const int wave = threadIdx.x / WAVE;
-    SearchMem& m = smem_search[wave];
+    TaskMem& m = smem_task[wave];
     const int lane = lane_id();
     const int64_t nt = (int64_t)*a.ntiles;
-    if (pass == 0) {
-        const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t t = nt + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.tile_cap;
-             t += nth)
-            a.leaf_cnt[t] = 0;
-    }
     const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
     for (int64_t t = blockIdx.x * (int64_t)TASK_WPB + wave; t < nt; t += nw) {
-        const Tile tl = a.tiles[t];
+        Tile tl = a.tiles[t];
+        tl.count = uniform(tl.count);
+        tl.box = uniform(tl.box);
         const bool skip = tl.count <= 0 || (fixup && a.tflag[t] == 0);
         if (skip) {
-            if (pass == 0 && lane == 0) {
+            if (lane == 0) {
                 a.leaf_cnt[t] = 0;
                 if (!fixup) a.trad[t] = 0.f;
             }
             continue;
         }
-        task_one<T, MODE>(a, m, tl, t, pass, fixup);
+        task_one<T, MODE>(a, m, tl, t, false, fixup, 0);
+    }
+}
+
+// Tiles whose list did not fit the LDS buffer: space of the counted size,
+// then the search again.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_ovf(TArgs<T> a, int fixup) {
+    __shared__ TaskMem smem_task[TASK_WPB];
+    const int wave = threadIdx.x / WAVE;
+    TaskMem& m = smem_task[wave];
+    const int64_t no = (int64_t)a.cnt->n_ovf;
+    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
+    for (int64_t q = blockIdx.x * (int64_t)TASK_WPB + wave; q < no; q += nw) {
+        const int64_t t = a.ovf[q];
+        Tile tl = a.tiles[t];
+        tl.count = uniform(tl.count);
+        tl.box = uniform(tl.box);
+        int64_t at = 0;
+        if (lane_id() == 0) {
+            const int64_t c = a.leaf_cnt[t];
+            at = (int64_t)atomicAdd(&a.cnt->leaf_used, (unsigned long long)c);
+            if (at + c > a.leaf_cap) {
+                a.leaf_cnt[t] = 0;
+                latch(a.cnt, SWSPH_ST_CAPACITY);
+                at = -1;
+            }
+            a.leaf_off[t] = (int32_t)at;
+        }
+        at = __shfl(at, 0, WAVE);
+        if (at < 0) continue;
+        task_one<T, MODE>(a, m, tl, t, true, fixup, at);
     }
 }
 
@@ -235,6 +291,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.leaf_cap = b.leaf_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
+    a.ovf = b.ovf;
     a.cnt = b.cnt;
     a.eps = (T)sc.eps;
     a.margin = (T)margin;
@@ -247,15 +304,14 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     if (b.n <= 0) return;
     const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? 1.25 : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
-    const dim3 grid(wave_grid(b.tile_cap, TASK_WPB)), block(TASK_WPB * WAVE);
-    void (*kern)(TArgs<T>, int, int) =
+    const dim3 block(TASK_WPB * WAVE);
+    void (*kern)(TArgs<T>, int) =
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
-    auto run = [&](int pass) {
-        hipLaunchKernelGGL(kern, grid, block, 0, s, a, pass, (int)fixup);
-    };
-    run(0);
-    launch_exclusive_scan(b.leaf_cnt, b.tile_cap, b.leaf_part, b.leaf_off, s);
-    run(1);
+    void (*kovf)(TArgs<T>, int) =
+        mode == 0 ? k_tasks_ovf<T, 0> : (mode == 1 ? k_tasks_ovf<T, 1> : k_tasks_ovf<T, 2>);
+    launch_fill_u32(&b.cnt->leaf_used, 4, 0u, s);  // leaf_used and n_ovf
+    hipLaunchKernelGGL(kern, dim3(wave_grid(b.tile_cap, TASK_WPB)), block, 0, s, a, (int)fixup);
+    hipLaunchKernelGGL(kovf, dim3(wave_grid(1024, TASK_WPB)), block, 0, s, a, (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
 template void launch_tasks<float>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);

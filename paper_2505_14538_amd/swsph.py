@@ -45,7 +45,12 @@ class Config(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("tile", ctypes.c_int32),
                 ("lds_cap", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("leaf_max", ctypes.c_int32), ("tile_dens", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("lds_cap_dens", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in
+                ("tile", "tile_dens", "lds_cap", "lds_cap_dens", "order", "leaf_max")]
 
 
 class ParticlesC(ctypes.Structure):
@@ -117,8 +122,7 @@ _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut)
                             _vp, _vp]
 _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
 _lib.swsph_autotune.argtypes = [_vp, _P(ParticlesC), _vp, _vp, ctypes.c_char_p]
-_lib.swsph_plan_get_tuning.argtypes = [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
-                                       _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]
+_lib.swsph_plan_get_tuning.argtypes = [_vp, _P(Tuning)]
 _lib.swsph_kernel_times.argtypes = [_vp, _P(ctypes.c_double), _P(ctypes.c_uint64), _vp]
 _lib.swsph_reset_timers.argtypes = [_vp]
 
@@ -392,11 +396,9 @@ class Plan:
         return self.tuning()
 
     def tuning(self):
-        a, b, c, d, e = (ctypes.c_int32() for _ in range(5))
-        _check(_lib.swsph_plan_get_tuning(self.h, ctypes.byref(a), ctypes.byref(b),
-                                          ctypes.byref(c), ctypes.byref(d), ctypes.byref(e)))
-        return {"tile": a.value, "tile_dens": e.value, "lds_cap": b.value, "order": c.value,
-                "leaf_max": d.value}
+        t = Tuning()
+        _check(_lib.swsph_plan_get_tuning(self.h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
 
 def host(d: Dict[str, object]) -> Dict[str, np.ndarray]:

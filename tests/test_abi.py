@@ -42,7 +42,8 @@ def test_version_and_defaults(S):
 @pytest.mark.parametrize("field,val", [("eta", 0.0), ("eps", -1.0), ("gamma", 1.0),
                                        ("alpha", -0.5), ("h_tol", 0.0), ("h_max_iter", 0),
                                        ("dtype", 7), ("tile", 24), ("lds_cap", 100),
-                                       ("order", 3), ("flags", 0x4 | 0x8), ("tile_dens", 12)])
+                                       ("order", 3), ("flags", 0x4 | 0x8), ("tile_dens", 12),
+                                       ("lds_cap_dens", 64)])
 def test_plan_rejects_bad_config(S, field, val):
     c = S.default_config()
     setattr(c, field, val)
