@@ -187,8 +187,13 @@ def run(args):
                                "sigma_ln=1.5 on 64^3 grid, periodic unit box, FP32",
                    "n": parts.n, "loops": "bin+density(Newton)+gradient+force"},
         "pairs": {"density": P_d, "gradient": P_g, "force": P_f},
+        # per loop: useful pairs over the loop kernels' time per step (the
+        # density loop runs its kernel once plus its fix-up passes)
         "rates": {k: {"pairs_per_s": {"density": P_d, "gradient": P_g, "force": P_f}[k] /
-                      (kt[k]["ms"] * 1e-3), "kernel_ms": kt[k]["ms"]} for k in kt},
+                      (kt[k]["ms"] * kt[k]["launches"] / args.steps * 1e-3),
+                      "kernel_ms_per_launch": kt[k]["ms"],
+                      "launches_per_step": kt[k]["launches"] / args.steps}
+                  for k in kt if k in ("density", "gradient", "force")},
         "frac_fp32_peak": frac_peak,
         "newton_sweeps_per_tile": sweeps,
         "per_task_launch": None if args.no_per_task else {
