@@ -67,7 +67,8 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
         const bool act = lane < tl.count;
         const T h = act ? a.hs[tl.begin + lane] : (T)0;
         const T hmax = wave_max(h);
-        R = (float)(a.eps * hmax * a.margin);
+        // float radius rounded up so it still covers every support of the tile
+        R = (float)(a.eps * hmax * a.margin * (T)(1 + 4e-7));
         if (!(R < Rcap)) {
             // fixed supports (every loop but the Newton density search) must fit
             if ((MODE != 0 || a.margin == (T)1) && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
