@@ -36,7 +36,6 @@ struct BinPtrs {
     unsigned long long* ntiles;  // its device count
     Tile* tiles_d;             // density tiles (may alias tiles)
     int32_t* order_d;
-    int32_t* dparent;          // density tile -> gradient/force tile holding it
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *leaf_cnt, *leaf_off;
     int32_t* ovf;

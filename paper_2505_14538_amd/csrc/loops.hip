@@ -51,26 +51,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     // root of sum_j w(q_ij) = Tt  <=>  h^3 n(h) = eta^3
     const T Tt = a.eta * a.eta * a.eta * eps * eps * eps / cnorm;
     const T tiny = (sizeof(T) == 4) ? (T)2.4e-7 : (T)4.5e-16;
-    // first pass: the tile shares the cell list of the gradient/force tile
-    // holding it (built with that tile's larger radius) and takes its own
-    // staged radius; fix-up passes: its own list and the radius set for it
-    int lt = t;
-    T R;
-    if (a.parent && !a.fixup) {
-        lt = uniform(a.parent[t]);
-        const T hm = wave_max(act ? a.hs[i] : (T)0);
-        R = eps * hm * (fixed ? (T)1 : (T)1.25);
-        if (!(R < Rcap)) {
-            if (fixed && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
-            R = Rcap;
-        }
-        if (!(R > (T)0)) R = Rcap;
-        // the radius travels as float: round it up so it still covers every
-        // support of the tile
-        R = (T)(float)(R * (T)(1 + 4e-7));
-    } else {
-        R = (T)a.trad[t];
-    }
+    const T R = (T)a.trad[t];
     const T hstage = R / eps;
     const T hedge = hstage * ((T)1 - (T)8 * tiny);  // largest h whose support is staged
     (void)L;
@@ -126,7 +107,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     };
     const T R2 = R * R;
     int flushes = 0;
-    int ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, R2, flushes, sweep);
+    int ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, flushes, sweep);
     sweep(ns);
     const bool cached = flushes == 0;
     for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
@@ -179,7 +160,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
             const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
             const T Rs = Hs < R ? Hs : R;
             int fl = 0;
-            ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, Rs * Rs, fl, sweep);
+            ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, Rs * Rs, fl, sweep);
             sweep(ns);
         }
     }
@@ -488,14 +469,7 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.d_out;
     a.iout = b.d_int;
-    if (bin.tiles_d != bin.tiles) {
-        // first pass: cell lists of the (fewer, larger) gradient/force tiles,
-        // shared by the density tiles inside them
-        launch_tasks<T>(bin, sc, 0, false, s);
-        a.parent = b.dparent;
-    } else {
-        launch_tasks<T>(b, sc, 0, false, s);
-    }
+    launch_tasks<T>(b, sc, 0, false, s);
     timer_begin(sc.timer, 0, s);
     int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
     timer_end(sc.timer, 0, s);

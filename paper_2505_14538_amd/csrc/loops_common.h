@@ -25,7 +25,6 @@ struct KArgs {
     const BoxInfo* boxtab;
     const Tile* tiles;
     const int32_t* order;      // task list: tile indices in queue order
-    const int32_t* parent;     // density first pass: tile -> tile whose cell list it shares
     const unsigned long long* ntask;  // its length (device)
     int64_t tile_cap;          // bound of the device tile count (cnt->n_tiles)
     int32_t task;              // per-task launch: the task to run
@@ -148,18 +147,17 @@ template <typename T> __device__ __forceinline__ int32_t as_int(T v);
 template <> __device__ __forceinline__ int32_t as_int<float>(float v) { return __float_as_int(v); }
 template <> __device__ __forceinline__ int32_t as_int<double>(double v) { return (int32_t)v; }
 
-// Stream the j-particles of task list lt through the lanes, cull them
+// Stream the j-particles of tile t's task list through the lanes, cull them
 // against the tile box (radius R, or the j-particle's own support for the
 // force loop), stage survivors in LDS; flush(nsurv) is called whenever the
 // buffer could overflow (the buffer is empty afterwards).  Returns the
 // number of staged survivors left for the caller.
 template <int LK, typename T, int CAP, class WM, class Flush>
-__device__ int stage_tile(WM& m, const KArgs<T>& a, int lt, const BoxInfo& bi, const TileGeom& g,
+__device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
                           T R2, int& flushes, Flush&& flush) {
     const int lane = lane_id();
-    const int64_t off = uniform(a.leaf_off[lt]);
-    int64_t nl = uniform(a.leaf_cnt[lt]);
-    if (off < 0) nl = 0;
+    const int64_t off = a.leaf_off[t];
+    int64_t nl = a.leaf_cnt[t];
     if (off + nl > a.leaf_cap) nl = a.leaf_cap > off ? a.leaf_cap - off : 0;
     const T L = (T)bi.L;
     int nsurv = 0;
@@ -292,7 +290,6 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.boxtab = b.boxtab;
     a.tiles = b.tiles;
     a.order = b.order;
-    a.parent = nullptr;
     a.ntask = b.ntiles;
     a.tile_cap = b.tile_cap;
     a.task = 0;
