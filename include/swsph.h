@@ -173,7 +173,7 @@ typedef struct swsph_stats {
     uint64_t newton_sweeps;      /* sum over density tiles of their sweeps */
     uint32_t newton_max;         /* largest sweep count of a tile */
     uint32_t newton_failed;      /* particles whose h did not converge */
-    uint64_t leaves;             /* cells emitted by the task searches */
+    uint64_t listed;             /* candidate entries written by the task builds */
     uint64_t restages;           /* density tiles that widened their search */
     uint64_t n_tiles_dens;       /* density tile tasks of the last bin */
     uint64_t reserved[5];

@@ -44,7 +44,7 @@ struct Geometry {
     int32_t tile_d = 8;     // most particles per density tile
     int64_t tile_cap = 0;   // most tiles the bin can make (one per particle)
     int64_t n_fine = 0, n_pyr = 0;
-    int64_t leaf_cap = 0;
+    int64_t cand_cap = 0;
     int tsz = 4;
     std::vector<BoxInfo> boxes;
     Layout lay{};
@@ -53,11 +53,11 @@ struct Geometry {
 constexpr int KMAX = 10;               // Morton key: 3 x 10 bits per box
 constexpr int64_t FINE_MAX = int64_t(1) << 29;
 
-// Task-list capacity: 48 cells per particle (cell tiles of <= 64 particles
-// need ~2-8 on clustered and uniform sets), below 2^31 (int32 offsets).
-// Overflow latches SWSPH_ST_CAPACITY.
-int64_t leaf_capacity(int64_t n) {
-    return std::min<int64_t>(48 * n + 4096, (int64_t(1) << 31) - 1);
+// Candidate-list capacity: 160 entries per particle (lists of cell tiles
+// hold ~30-80 per particle on the clustered and uniform sets), below 2^31
+// (int32 offsets).  Overflow latches SWSPH_ST_CAPACITY.
+int64_t cand_capacity(int64_t n) {
+    return std::min<int64_t>(160 * n + 65536, (int64_t(1) << 31) - 1);
 }
 
 int choose_k(int64_t nb) {
@@ -138,11 +138,11 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.order_d = take(4 * (uint64_t)toff);
     l.ord_table = take(4 * (uint64_t)order_table_size(toff));
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
-    l.leaf_cnt = take(4 * (uint64_t)(toff + 1));
-    l.leaf_off = take(4 * (uint64_t)(toff + 2));
+    l.cand_cnt = take(4 * (uint64_t)(toff + 1));
+    l.cand_off = take(4 * (uint64_t)(toff + 2));
     l.ovf = take(4 * (uint64_t)toff);
-    G.leaf_cap = leaf_capacity(n);
-    l.leaves = take(8 * (uint64_t)G.leaf_cap);
+    G.cand_cap = cand_capacity(n);
+    l.cands = take(4 * (uint64_t)G.cand_cap);
     l.trad = take(4 * (uint64_t)toff);
     l.tflag = take(4 * (uint64_t)toff);
     l.d_out = take(10 * T * N);
@@ -300,11 +300,11 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.order_d = same ? b.order : (int32_t*)(w + l.order_d);
     b.ord_table = (int32_t*)(w + l.ord_table);
     b.ord_base = (int32_t*)(w + l.ord_base);
-    b.leaf_cnt = (int32_t*)(w + l.leaf_cnt);
-    b.leaf_off = (int32_t*)(w + l.leaf_off);
+    b.cand_cnt = (int32_t*)(w + l.cand_cnt);
+    b.cand_off = (int32_t*)(w + l.cand_off);
     b.ovf = (int32_t*)(w + l.ovf);
-    b.leaves = (int2*)(w + l.leaves);
-    b.leaf_cap = pl->G.leaf_cap;
+    b.cands = (uint32_t*)(w + l.cands);
+    b.cand_cap = pl->G.cand_cap;
     b.trad = (float*)(w + l.trad);
     b.tflag = (int32_t*)(w + l.tflag);
     b.d_out = w + l.d_out;
@@ -627,7 +627,7 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
     out->newton_sweeps = c.newton_sweeps;
     out->newton_max = (uint32_t)c.newton_max;
     out->newton_failed = (uint32_t)c.newton_failed;
-    out->leaves = c.leaves;
+    out->listed = c.listed;
     out->restages = c.restages;
     out->n_tiles_dens = c.n_tiles_d;
     if (c.status & SWSPH_ST_DOMAIN) return fail(SWSPH_E_DOMAIN, "a particle lies outside its box");

@@ -37,10 +37,10 @@ struct BinPtrs {
     Tile* tiles_d;             // density tiles (may alias tiles)
     int32_t* order_d;
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
-    int32_t *leaf_cnt, *leaf_off;
+    int32_t *cand_cnt, *cand_off;
     int32_t* ovf;
-    int2* leaves;
-    int64_t leaf_cap;
+    uint32_t* cands;
+    int64_t cand_cap;
     float* trad;
     int32_t* tflag;
     void *d_out, *g_out, *f_out, *adj;

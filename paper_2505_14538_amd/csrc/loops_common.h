@@ -15,9 +15,6 @@ template <typename T, int CAP, int NV>
 struct WaveMem {
     V4<T> s[NV][CAP];          // staged j-particles
     uint16_t lst[LC][WAVE];    // per-lane hit lists (staged indices), column per lane
-    int32_t lbeg[WAVE];        // current batch of task-list leaves
-    int32_t lpre[WAVE + 1];
-    int32_t lshift[WAVE];
 };
 
 template <typename T>
@@ -28,10 +25,10 @@ struct KArgs {
     const unsigned long long* ntask;  // its length (device)
     int64_t tile_cap;          // bound of the device tile count (cnt->n_tiles)
     int32_t task;              // per-task launch: the task to run
-    const int32_t* leaf_cnt;
-    const int32_t* leaf_off;
-    const int2* leaves;
-    int64_t leaf_cap;
+    const int32_t* cand_cnt;
+    const int32_t* cand_off;
+    const uint32_t* cands;
+    int64_t cand_cap;
     float* trad;
     int32_t* tflag;
     const V4<T>* pos4;
@@ -147,107 +144,93 @@ template <typename T> __device__ __forceinline__ int32_t as_int(T v);
 template <> __device__ __forceinline__ int32_t as_int<float>(float v) { return __float_as_int(v); }
 template <> __device__ __forceinline__ int32_t as_int<double>(double v) { return (int32_t)v; }
 
-// Stream the j-particles of tile t's task list through the lanes, cull them
-// against the tile box (radius R, or the j-particle's own support for the
-// force loop), stage survivors in LDS; flush(nsurv) is called whenever the
+// Stream tile t's candidate list through the lanes (coalesced entries,
+// gathers of the j-data), cull against the tile box (radius R, or the
+// j-particle's own support for the symmetric loops; the list was culled with
+// the build radius already, so this only matters when the caller passes a
+// smaller R), stage survivors in LDS; flush(nsurv) is called whenever the
 // buffer could overflow (the buffer is empty afterwards).  Returns the
 // number of staged survivors left for the caller.
 template <int LK, typename T, int CAP, class WM, class Flush>
 __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
                           T R2, int& flushes, Flush&& flush) {
     const int lane = lane_id();
-    const int64_t off = a.leaf_off[t];
-    int64_t nl = a.leaf_cnt[t];
-    if (off + nl > a.leaf_cap) nl = a.leaf_cap > off ? a.leaf_cap - off : 0;
+    const int64_t off = uniform(a.cand_off[t]);
+    int64_t nc = uniform(a.cand_cnt[t]);
+    if (off < 0) nc = 0;
+    if (off + nc > a.cand_cap) nc = a.cand_cap > off ? a.cand_cap - off : 0;
     const T L = (T)bi.L;
     int nsurv = 0;
     flushes = 0;
-    for (int64_t lb = 0; lb < nl; lb += WAVE) {
-        const int nb = (int)min((int64_t)WAVE, nl - lb);
-        int32_t beg = 0, num = 0;
-        int sh = 13;
-        if (lane < nb) unpack_leaf(a.leaves[off + lb + lane], beg, num, sh);
-        int total;
-        const int e = wave_excl_scan(num, total);
-        m.lbeg[lane] = beg;
-        m.lpre[lane] = e;
-        m.lshift[lane] = sh;
-        if (lane == 0) m.lpre[WAVE] = total;
-        wave_sync();
-        for (int base = 0; base < total; base += WAVE) {
-            if (nsurv + WAVE > CAP) {
-                flush(nsurv);
-                nsurv = 0;
-                ++flushes;
-            }
-            const int v = base + lane;
-            bool pass = false;
-            V4<T> pa;
-            T xs = 0, ys = 0, zs = 0;
-            int j = 0;
-            if (v < total) {
-                int lo = 0, hi = nb - 1;
-                while (lo < hi) {  // last leaf whose prefix is <= v
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
-                }
-                j = m.lbeg[lo] + (v - m.lpre[lo]);
-                if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid task list
-                int sx, sy, sz;
-                shift_of(m.lshift[lo], sx, sy, sz);
-                pa = a.pos4[j];
-                xs = pa.x + (T)sx * L;
-                ys = pa.y + (T)sy * L;
-                zs = pa.z + (T)sz * L;
-                const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
-                const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
-                const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
-                const T d2 = dist2_unfused(gx, gy, gz);
-                T crit = R2;
-                if (Symmetric<LK>::value) {
-                    const T Hj = mul_unfused(a.eps, a.hs[j]);
-                    crit = max(crit, mul_unfused(Hj, Hj));
-                }
-                pass = d2 < crit;
-            }
-            const unsigned long long pm = ballot(pass);
-            if (pass) {
-                const int k = nsurv + mbcnt(pm);
-                const V4<T> va = a.vel4[j];
-                if (LK == L_DENS) {
-                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
-                    m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
-                } else if (LK == L_GRAD) {
-                    const V4<T> da = a.dens4[j];  // (rho, f, c, A)
-                    m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
-                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                    m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
-                } else if (LK == L_FORCE) {
-                    const V4<T> da = a.dens4[j];
-                    const T Hj = mul_unfused(a.eps, a.hs[j]);
-                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                    m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
-                    m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
-                } else if (LK == L_ADJA) {
-                    const V4<T> da = a.dens4[j];   // (rho, f, c, A)
-                    const V4<T> wj = a.aux4[j];    // (dL/dax, dL/day, dL/daz, dL/ddu)
-                    const T Hj = mul_unfused(a.eps, a.hs[j]);
-                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                    m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                    m.s[2][k] = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
-                    m.s[3][k] = V4<T>{da.x, wj.x, wj.y, wj.z};
-                    m.s[4][k] = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
-                } else {
-                    // density adjoint: (m, rho_bar, rho'_bar, 1/H); implicit h: (lambda h^3, 1/H, idx, 0)
-                    const T Hj = mul_unfused(a.eps, a.hs[j]);
-                    m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                    m.s[1][k] = a.aux4[j];
-                }
-            }
-            nsurv += __popcll(pm);
-            wave_sync();
+    for (int64_t base = 0; base < nc; base += WAVE) {
+        if (nsurv + WAVE > CAP) {
+            flush(nsurv);
+            nsurv = 0;
+            ++flushes;
         }
+        const int64_t v = base + lane;
+        bool pass = false;
+        V4<T> pa;
+        T xs = 0, ys = 0, zs = 0;
+        int j = 0;
+        if (v < nc) {
+            const uint32_t e = a.cands[off + v];
+            j = (int)(e & 0x3ffffffu);
+            if (j >= a.n) j = 0;  // cannot happen with a valid list
+            int sx, sy, sz;
+            shift_of((int)(e >> 26), sx, sy, sz);
+            pa = a.pos4[j];
+            xs = pa.x + (T)sx * L;
+            ys = pa.y + (T)sy * L;
+            zs = pa.z + (T)sz * L;
+            const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+            const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+            const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+            const T d2 = dist2_unfused(gx, gy, gz);
+            T crit = R2;
+            if (Symmetric<LK>::value) {
+                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                crit = max(crit, mul_unfused(Hj, Hj));
+            }
+            pass = d2 < crit;
+        }
+        const unsigned long long pm = ballot(pass);
+        if (pass) {
+            const int k = nsurv + mbcnt(pm);
+            const V4<T> va = a.vel4[j];
+            if (LK == L_DENS) {
+                m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
+                m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
+            } else if (LK == L_GRAD) {
+                const V4<T> da = a.dens4[j];  // (rho, f, c, A)
+                m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
+                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
+            } else if (LK == L_FORCE) {
+                const V4<T> da = a.dens4[j];
+                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
+                m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
+            } else if (LK == L_ADJA) {
+                const V4<T> da = a.dens4[j];   // (rho, f, c, A)
+                const V4<T> wj = a.aux4[j];    // (dL/dax, dL/day, dL/daz, dL/ddu)
+                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
+                m.s[2][k] = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
+                m.s[3][k] = V4<T>{da.x, wj.x, wj.y, wj.z};
+                m.s[4][k] = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
+            } else {
+                // density adjoint: (m, rho_bar, rho'_bar, 1/H); implicit h: (lambda h^3, 1/H, idx, 0)
+                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                m.s[1][k] = a.aux4[j];
+            }
+        }
+        nsurv += __popcll(pm);
+        wave_sync();
     }
     return nsurv;
 }
@@ -293,10 +276,10 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.ntask = b.ntiles;
     a.tile_cap = b.tile_cap;
     a.task = 0;
-    a.leaf_cnt = b.leaf_cnt;
-    a.leaf_off = b.leaf_off;
-    a.leaves = b.leaves;
-    a.leaf_cap = b.leaf_cap;
+    a.cand_cnt = b.cand_cnt;
+    a.cand_off = b.cand_off;
+    a.cands = b.cands;
+    a.cand_cap = b.cand_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
     a.pos4 = (const V4<T>*)b.pos4;

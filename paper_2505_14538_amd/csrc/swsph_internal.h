@@ -52,14 +52,14 @@ struct Counters {
     unsigned long long newton_sweeps;
     unsigned long long newton_max;
     unsigned long long newton_failed;
-    unsigned long long leaves;
+    unsigned long long listed;
     unsigned long long restages;
     unsigned long long queue[4][8];    // task-queue heads per loop (8: one per XCD segment)
     unsigned long long leaf_need;      // leaves requested by the last task build
     unsigned long long n_tiles;        // tiles of the gradient/force (and adjoint) loops
     unsigned long long n_tiles_d;      // tiles of the density loop
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
-    unsigned long long leaf_used;      // task-list entries taken by the current build
+    unsigned long long cand_used;      // task-list entries taken by the current build
     unsigned long long n_ovf;          // tiles of the current build whose list overflowed LDS
     unsigned long long reserved[4];
 };
@@ -74,7 +74,7 @@ struct Layout {
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
     uint64_t tiles, order, tiles_d, order_d, ord_table, ord_base;
     // task lists (CSR of cells per tile) and density fix-up state
-    uint64_t leaf_cnt, leaf_off, leaves, trad, tflag, ovf;
+    uint64_t cand_cnt, cand_off, cands, trad, tflag, ovf;
     // sorted-order results
     uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
     uint64_t d_int;     // 2 arrays of int32: nngb iters

@@ -1,12 +1,11 @@
-// tasks.hip -- device task lists: for every i-tile, the cells (leaves of the
-// recursive cell search, see search.h) its loop must visit, stored as a CSR:
-// leaf_off[t] .. leaf_off[t] + leaf_cnt[t] in `leaves`.
-//
-// Built in two passes (count, then fill after an exclusive scan of the
-// counts) so the list needs no atomics and comes out in a fixed order.  The
-// count pass also fixes the tile's search radius (trad), which the loop
-// kernels reuse for their per-particle cull, and a cost estimate
-// (tile particles x candidate particles) for task ordering.
+// tasks.hip -- device task lists: for every i-tile, the candidate
+// j-particles its loop must visit (from the recursive cell search of
+// search.h, culled against the tile box), stored as cand_off[t] ..
+// cand_off[t] + cand_cnt[t] in `cands`.  One search per tile; lists are
+// contiguous per tile and placed by a bump counter (their content and order
+// do not depend on the placement).  The build also fixes the tile's search
+// radius (trad), which the loop kernels reuse, and a cost estimate (tile
+// particles x candidates) for task ordering.
 #include "launch.h"
 #include "search.h"
 
@@ -23,10 +22,10 @@ struct TArgs {
     const int32_t* cstart;
     const float* hpyr;
     const T* hs;
-    int32_t* leaf_cnt;
-    int32_t* leaf_off;
-    int2* leaves;
-    int64_t leaf_cap;
+    int32_t* cand_cnt;
+    int32_t* cand_off;
+    uint32_t* cands;
+    int64_t cand_cap;
     float* trad;
     const int32_t* tflag;
     int32_t* ovf;               // tiles whose list overflowed the LDS buffer
@@ -34,23 +33,30 @@ struct TArgs {
     T eps;
     T margin;
     int32_t leaf_max;
+    const V4<T>* pos4;
+    int64_t n;
 };
 
-// Task list of tile t from one cell search.  Main pass: the tile's leaves
-// are gathered in LDS (up to TASK_BUF) and copied to space taken from a
-// device bump counter, so each tile's list is contiguous; its radius and
-// cost are recorded.  A tile with more leaves only counts them and is put
-// on the overflow list; the overflow pass takes exactly that much space and
-// runs its search again, writing straight to global memory.
-// Wavefront-uniform.
+// Task list of tile t: its candidate j-particles -- the particles of the
+// cells the cell search keeps whose distance to the tile's bounding box is
+// below the loop's radius R (force: below max(R, H_j), the symmetric
+// support) -- as entries j | image << 26 (periodic image code, see
+// search.h).  The cull is done once here, so the loops only gather.
+// Main pass: a tile's entries collect in LDS (up to TASK_BUF) and are copied
+// to space taken from a device bump counter, so each list is contiguous; the
+// tile's radius and cost (particles x candidates) are recorded.  A longer
+// list is only counted and put on the overflow list; the overflow pass takes
+// exactly that much space and runs the search again, writing straight to
+// global memory.  Wavefront-uniform.
 #ifndef SWSPH_TASK_BUF
-#define SWSPH_TASK_BUF 512
+#define SWSPH_TASK_BUF 2048
 #endif
-constexpr int TASK_BUF = SWSPH_TASK_BUF;  // leaves buffered in LDS per wavefront
+constexpr int TASK_BUF = SWSPH_TASK_BUF;  // entries buffered in LDS per wavefront
 
 struct TaskMem {
     SearchMem sm;
-    int2 buf[TASK_BUF];
+    int32_t lpre[LEAFCAP + 1];  // prefix sums of the particle counts of a leaf batch
+    uint32_t buf[TASK_BUF];
 };
 
 template <typename T, int MODE>
@@ -85,25 +91,67 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
     SearchState st;
     search_init(m.sm, st, bi, g, Rstart);
     const float R2 = R * R;
-    int64_t total = 0, cand = 0;
-    const int64_t mine = overflow_pass ? (int64_t)a.leaf_cnt[t] : 0;
+    const T Rt = (T)R;
+    const T R2t = Rt * Rt;  // the loops cull with the same value
+    const T Lt = (T)bi.L;
+    int64_t total = 0;
+    const int64_t mine = overflow_pass ? (int64_t)a.cand_cnt[t] : 0;
     for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
         const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr,
                                                  a.leaf_max, a.cnt);
         if (st.nleaf > 0) {
-            int c = 0;
-            for (int k = lane; k < st.nleaf; k += WAVE) {
-                const int64_t at = total + k;
-                const int2 v = pack_leaf(m.sm.lbeg[k], m.sm.lcnt[k], m.sm.lshift[k]);
-                if (overflow_pass) {
-                    if (at < mine && base + at < a.leaf_cap) a.leaves[base + at] = v;
-                } else if (at < TASK_BUF) {
-                    m.buf[at] = v;
+            // prefix sums of the batch's particle counts (two lanes' worth each)
+            int c0 = lane < st.nleaf ? m.sm.lcnt[lane] : 0;
+            int c1 = lane + WAVE < st.nleaf ? m.sm.lcnt[lane + WAVE] : 0;
+            int tot0 = 0, tot1 = 0;
+            const int e0 = wave_excl_scan(c0, tot0);
+            const int e1 = wave_excl_scan(c1, tot1);
+            m.lpre[lane] = e0;
+            m.lpre[lane + WAVE] = tot0 + e1;
+            if (lane == 0) m.lpre[2 * WAVE] = tot0 + tot1;
+            wave_sync();
+            const int nl = st.nleaf;
+            const int nv = tot0 + tot1;
+            for (int v0 = 0; v0 < nv; v0 += WAVE) {
+                const int v = v0 + lane;
+                bool pass = false;
+                uint32_t ent = 0;
+                if (v < nv) {
+                    int lo = 0, hi = nl - 1;
+                    while (lo < hi) {  // last leaf whose prefix is <= v
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                    }
+                    int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
+                    if (j < 0 || j >= (int)a.n) j = 0;  // cannot happen with a valid cell table
+                    const int code = m.sm.lshift[lo];
+                    int sx, sy, sz;
+                    shift_of(code, sx, sy, sz);
+                    const V4<T> pa = a.pos4[j];
+                    const T xs = pa.x + (T)sx * Lt, ys = pa.y + (T)sy * Lt, zs = pa.z + (T)sz * Lt;
+                    const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+                    const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+                    const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+                    const T d2 = dist2_unfused(gx, gy, gz);
+                    T crit = R2t;
+                    if (MODE == 2) {
+                        const T Hj = mul_unfused(a.eps, a.hs[j]);
+                        crit = max(crit, mul_unfused(Hj, Hj));
+                    }
+                    pass = d2 < crit;
+                    ent = (uint32_t)j | ((uint32_t)code << 26);
                 }
-                c += m.sm.lcnt[k];
+                const unsigned long long pm = ballot(pass);
+                if (pass) {
+                    const int64_t at = total + mbcnt(pm);
+                    if (overflow_pass) {
+                        if (at < mine && base + at < a.cand_cap) a.cands[base + at] = ent;
+                    } else if (at < TASK_BUF) {
+                        m.buf[at] = ent;
+                    }
+                }
+                total += __popcll(pm);
             }
-            cand += wave_sum(c);
-            total += st.nleaf;
             st.nleaf = 0;
             wave_sync();
         }
@@ -112,25 +160,25 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
     if (!overflow_pass) {
         int64_t at = 0;
         if (lane == 0) {
-            a.leaf_cnt[t] = (int32_t)total;
-            a.tiles[t].cost = (float)tl.count * (float)cand;
-            atomicAdd(&a.cnt->leaves, (unsigned long long)total);
+            a.cand_cnt[t] = (int32_t)total;
+            a.tiles[t].cost = (float)tl.count * (float)total;
+            atomicAdd(&a.cnt->listed, (unsigned long long)total);
             if (total > TASK_BUF) {
-                a.leaf_off[t] = -1;
+                a.cand_off[t] = -1;
                 a.ovf[atomicAdd(&a.cnt->n_ovf, 1ull)] = (int32_t)t;
             } else {
-                at = (int64_t)atomicAdd(&a.cnt->leaf_used, (unsigned long long)total);
-                a.leaf_off[t] = at + total <= a.leaf_cap ? (int32_t)at : -1;
-                if (at + total > a.leaf_cap) {
-                    a.leaf_cnt[t] = 0;
+                at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
+                a.cand_off[t] = at + total <= a.cand_cap ? (int32_t)at : -1;
+                if (at + total > a.cand_cap) {
+                    a.cand_cnt[t] = 0;
                     latch(a.cnt, SWSPH_ST_CAPACITY);
                 }
             }
         }
         at = __shfl(at, 0, WAVE);
-        if (total <= TASK_BUF && at + total <= a.leaf_cap)
-            for (int k = lane; k < total; k += WAVE) a.leaves[at + k] = m.buf[k];
-    } else if (lane == 0 && base + total > a.leaf_cap) {
+        if (total <= TASK_BUF && at + total <= a.cand_cap)
+            for (int k = lane; k < total; k += WAVE) a.cands[at + k] = m.buf[k];
+    } else if (lane == 0 && base + total > a.cand_cap) {
         latch(a.cnt, SWSPH_ST_CAPACITY);
     }
     wave_sync();
@@ -154,7 +202,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
         const bool skip = tl.count <= 0 || (fixup && a.tflag[t] == 0);
         if (skip) {
             if (lane == 0) {
-                a.leaf_cnt[t] = 0;
+                a.cand_cnt[t] = 0;
                 if (!fixup) a.trad[t] = 0.f;
             }
             continue;
@@ -179,14 +227,14 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_ovf(TArgs<T> a, int f
         tl.box = uniform(tl.box);
         int64_t at = 0;
         if (lane_id() == 0) {
-            const int64_t c = a.leaf_cnt[t];
-            at = (int64_t)atomicAdd(&a.cnt->leaf_used, (unsigned long long)c);
-            if (at + c > a.leaf_cap) {
-                a.leaf_cnt[t] = 0;
+            const int64_t c = a.cand_cnt[t];
+            at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)c);
+            if (at + c > a.cand_cap) {
+                a.cand_cnt[t] = 0;
                 latch(a.cnt, SWSPH_ST_CAPACITY);
                 at = -1;
             }
-            a.leaf_off[t] = (int32_t)at;
+            a.cand_off[t] = (int32_t)at;
         }
         at = __shfl(at, 0, WAVE);
         if (at < 0) continue;
@@ -286,10 +334,10 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.cstart = b.cstart;
     a.hpyr = b.hmaxpyr;
     a.hs = (const T*)b.hs;
-    a.leaf_cnt = b.leaf_cnt;
-    a.leaf_off = b.leaf_off;
-    a.leaves = b.leaves;
-    a.leaf_cap = b.leaf_cap;
+    a.cand_cnt = b.cand_cnt;
+    a.cand_off = b.cand_off;
+    a.cands = b.cands;
+    a.cand_cap = b.cand_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
     a.ovf = b.ovf;
@@ -297,6 +345,8 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.eps = (T)sc.eps;
     a.margin = (T)margin;
     a.leaf_max = sc.leaf_max;
+    a.pos4 = (const V4<T>*)b.pos4;
+    a.n = b.n;
     return a;
 }
 
@@ -310,7 +360,7 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
     void (*kovf)(TArgs<T>, int) =
         mode == 0 ? k_tasks_ovf<T, 0> : (mode == 1 ? k_tasks_ovf<T, 1> : k_tasks_ovf<T, 2>);
-    launch_fill_u32(&b.cnt->leaf_used, 4, 0u, s);  // leaf_used and n_ovf
+    launch_fill_u32(&b.cnt->cand_used, 4, 0u, s);  // cand_used and n_ovf
     hipLaunchKernelGGL(kern, dim3(wave_grid(b.tile_cap, TASK_WPB)), block, 0, s, a, (int)fixup);
     hipLaunchKernelGGL(kovf, dim3(wave_grid(1024, TASK_WPB)), block, 0, s, a, (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);

@@ -90,7 +90,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
                 ("pairs_tested", ctypes.c_uint64 * 4), ("pairs_inside", ctypes.c_uint64 * 4),
                 ("newton_sweeps", ctypes.c_uint64), ("newton_max", ctypes.c_uint32),
-                ("newton_failed", ctypes.c_uint32), ("leaves", ctypes.c_uint64),
+                ("newton_failed", ctypes.c_uint32), ("listed", ctypes.c_uint64),
                 ("restages", ctypes.c_uint64), ("n_tiles_dens", ctypes.c_uint64),
                 ("reserved", ctypes.c_uint64 * 5)]
 
@@ -98,7 +98,7 @@ class Stats(ctypes.Structure):
         return {"status": self.status, "n_tiles": self.n_tiles,
                 "pairs_tested": list(self.pairs_tested), "pairs_inside": list(self.pairs_inside),
                 "newton_sweeps": self.newton_sweeps, "newton_max": self.newton_max,
-                "newton_failed": self.newton_failed, "leaves": self.leaves,
+                "newton_failed": self.newton_failed, "listed": self.listed,
                 "restages": self.restages, "n_tiles_dens": self.n_tiles_dens}
 
 
