@@ -62,10 +62,11 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -176,10 +177,10 @@ __device__ void adja_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t) {
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJA, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
-    gvx = stream_sum(gvx, T_i); gvy = stream_sum(gvy, T_i); gvz = stream_sum(gvz, T_i);
-    gm = stream_sum(gm, T_i); gA = stream_sum(gA, T_i); gf = stream_sum(gf, T_i);
-    gc = stream_sum(gc, T_i); grho = stream_sum(grho, T_i); gh = stream_sum(gh, T_i);
+    gx = stream_sum(gx, q); gy = stream_sum(gy, q); gz = stream_sum(gz, q);
+    gvx = stream_sum(gvx, q); gvy = stream_sum(gvy, q); gvz = stream_sum(gvz, q);
+    gm = stream_sum(gm, q); gA = stream_sum(gA, q); gf = stream_sum(gf, q);
+    gc = stream_sum(gc, q); grho = stream_sum(grho, q); gh = stream_sum(gh, q);
     if (lead) {
         AdjPtrs<T> J{a.out, a.n};
         J.arr(AJ_GX)[i] = gx;
@@ -207,10 +208,11 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const T h = a.hs[i];
@@ -268,8 +270,8 @@ __device__ void adjc_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJC, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
-    gm = stream_sum(gm, T_i); gh = stream_sum(gh, T_i);
+    gx = stream_sum(gx, q); gy = stream_sum(gy, q); gz = stream_sum(gz, q);
+    gm = stream_sum(gm, q); gh = stream_sum(gh, q);
     if (lead) {
         J.arr(AJ_GX)[i] += gx;
         J.arr(AJ_GX + 1)[i] += gy;
@@ -294,10 +296,11 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const T h = a.hs[i];
@@ -339,7 +342,7 @@ __device__ void adjd_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const T R = (T)a.trad[t];
     const int ns = stage_tile<L_ADJD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    gx = stream_sum(gx, T_i); gy = stream_sum(gy, T_i); gz = stream_sum(gz, T_i);
+    gx = stream_sum(gx, q); gy = stream_sum(gy, q); gz = stream_sum(gz, q);
     if (lead) {
         J.arr(AJ_GX)[i] += gx;
         J.arr(AJ_GX + 1)[i] += gy;

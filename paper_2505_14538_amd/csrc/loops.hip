@@ -34,10 +34,11 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     if (tl.count <= 0) return;
     if (a.fixup && a.tflag[t] == 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -112,7 +113,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
     const bool cached = flushes == 0;
     for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
         ++iters;
-        const T S0r = stream_sum(S0, T_i), S1r = stream_sum(S1, T_i);
+        const T S0r = stream_sum(S0, q), S1r = stream_sum(S1, q);
         if (!conv && !pend) {
             const T G = S0r;
             if (fabs(G - Tt) <= a.h_tol * Tt) {
@@ -164,15 +165,15 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
             sweep(ns);
         }
     }
-    S0 = stream_sum(S0, T_i);
-    S1 = stream_sum(S1, T_i);
-    Sr = stream_sum(Sr, T_i);
-    Sdr = stream_sum(Sdr, T_i);
-    Dv = stream_sum(Dv, T_i);
-    Cx = stream_sum(Cx, T_i);
-    Cy = stream_sum(Cy, T_i);
-    Cz = stream_sum(Cz, T_i);
-    cnt = stream_sum(cnt, T_i);
+    S0 = stream_sum(S0, q);
+    S1 = stream_sum(S1, q);
+    Sr = stream_sum(Sr, q);
+    Sdr = stream_sum(Sdr, q);
+    Dv = stream_sum(Dv, q);
+    Cx = stream_sum(Cx, q);
+    Cy = stream_sum(Cy, q);
+    Cz = stream_sum(Cz, q);
+    cnt = stream_sum(cnt, q);
     const bool last = a.fixup == 2;
     if (pend && last) { failed = true; pend = false; }
     if (!conv && !pend && act) failed = true;
@@ -235,10 +236,11 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -284,9 +286,9 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
     int flushes = 0;
     const int ns = stage_tile<L_GRAD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    vsig = stream_max(vsig, T_i);
-    lap = stream_sum(lap, T_i);
-    inside = stream_sum(inside, T_i);
+    vsig = stream_max(vsig, q);
+    lap = stream_sum(lap, q);
+    inside = stream_sum(inside, q);
     if (lead) {
         const T k5 = (T)(8.0 / PI_D) * invH * invH * invH * invH * invH;
         a.out[0 * a.n + i] = vsig;
@@ -309,10 +311,11 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     tl.box = uniform(tl.box);
     if (tl.count <= 0) return;
     const int lane = lane_id();
-    const int T_i = islots_of(tl.count), li = lane & (T_i - 1), js = lane / T_i, S = WAVE / T_i;
-    const bool act = li < tl.count;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? li : 0);
+    const int i = tl.begin + (act ? q.li : 0);
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     const V4<T> vi = a.vel4[i];
@@ -379,11 +382,11 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
     int flushes = 0;
     const int ns = stage_tile<L_FORCE, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
     sweep(ns);
-    ax = stream_sum(ax, T_i);
-    ay = stream_sum(ay, T_i);
-    az = stream_sum(az, T_i);
-    du = stream_sum(du, T_i);
-    nint = stream_sum(hits, T_i) - 1;
+    ax = stream_sum(ax, q);
+    ay = stream_sum(ay, q);
+    az = stream_sum(az, q);
+    du = stream_sum(du, q);
+    nint = stream_sum(hits, q) - 1;
     if (lead) {
         a.out[0 * a.n + i] = ax;
         a.out[1 * a.n + i] = ay;

@@ -48,29 +48,44 @@ struct KArgs {
     int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
 };
 
-// Lane mapping of a tile of c particles: i-slots = the power of two >= c,
-// streams = 64 / i-slots.
-__device__ __forceinline__ int islots_of(int c) {
-    int t = 1;
-    while (t < c && t < WAVE) t <<= 1;
-    return t;
+// Lane mapping of a tile of c particles (c <= 64): c i-slots times S =
+// floor(64 / c) streams, lane = i-slot + c * stream; the 64 - S c lanes
+// left over are unused (their tests are off).  Each stream of an i-particle
+// walks every S-th staged j-particle.
+struct LaneMap {
+    int T_i, S, li, js;
+    __device__ __forceinline__ bool used() const { return js < S; }
+};
+__device__ __forceinline__ LaneMap lane_map(int c) {
+    LaneMap q;
+    q.T_i = c < 1 ? 1 : (c > WAVE ? WAVE : c);
+    q.S = WAVE / q.T_i;
+    const int lane = lane_id();
+    q.js = lane / q.T_i;
+    q.li = lane - q.js * q.T_i;
+    return q;
 }
 
-// Lane mapping of a tile body: lane = i-slot + tile * stream.  Each of the
-// 64/tile streams of an i-particle walks every (64/tile)-th staged
-// j-particle; the partial sums of the streams are combined with xor
-// shuffles (lanes l and l ^ m share their i-slot when m is a multiple of
-// the tile size).
-template <typename V> __device__ __forceinline__ V stream_sum(V v, int tile) {
-    for (int m = tile; m < WAVE; m <<= 1) v += shfl_xor(v, m);
-    return v;
-}
-template <typename V> __device__ __forceinline__ V stream_max(V v, int tile) {
-    for (int m = tile; m < WAVE; m <<= 1) {
-        const V o = shfl_xor(v, m);
-        v = o > v ? o : v;
+// Sum (max) over the streams of each i-slot, returned in every lane of the
+// slot: a tree over stream indices with lane permutes (fixed order, so the
+// result is deterministic), then a broadcast from the slot's stream 0.
+template <typename V> __device__ __forceinline__ V stream_sum(V v, const LaneMap& q) {
+    const int lane = lane_id();
+    for (int m = 1; m < q.S; m <<= 1) {
+        const int src = q.li + q.T_i * (q.js + m);
+        const V o = __shfl(v, src < WAVE ? src : lane, WAVE);
+        if ((q.js & (2 * m - 1)) == 0 && q.js + m < q.S) v += o;
     }
-    return v;
+    return __shfl(v, q.li, WAVE);
+}
+template <typename V> __device__ __forceinline__ V stream_max(V v, const LaneMap& q) {
+    const int lane = lane_id();
+    for (int m = 1; m < q.S; m <<= 1) {
+        const int src = q.li + q.T_i * (q.js + m);
+        const V o = __shfl(v, src < WAVE ? src : lane, WAVE);
+        if ((q.js & (2 * m - 1)) == 0 && q.js + m < q.S && o > v) v = o;
+    }
+    return __shfl(v, q.li, WAVE);
 }
 
 // Pair loop over the staged j-particles with per-lane compaction.  Lane
