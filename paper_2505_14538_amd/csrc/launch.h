@@ -36,6 +36,7 @@ struct BinPtrs {
     unsigned long long* ntiles;  // its device count
     Tile* tiles_d;             // density tiles (may alias tiles)
     int32_t* order_d;
+    int32_t* dfirst;           // first density tile of each gradient/force tile (+ end)
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *cand_cnt, *cand_off;
     int32_t* ovf;
@@ -84,6 +85,9 @@ void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, 
 // tasks.hip: mode 0 density, 1 gradient, 2 force; fixup: only flagged tiles
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s);
+template <typename T>
+void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s);
+void launch_order(const BinPtrs& b, hipStream_t s);
 int64_t order_table_size(int64_t tile_cap);
 
 // loops.hip

@@ -472,7 +472,12 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.d_out;
     a.iout = b.d_int;
-    launch_tasks<T>(b, sc, 0, false, s);
+    if (bin.tiles_d != bin.tiles) {
+        launch_tasks_grouped<T>(bin, sc, s);  // one search per gradient/force tile
+        if (sc.order == 0) launch_order(b, s);
+    } else {
+        launch_tasks<T>(b, sc, 0, false, s);
+    }
     timer_begin(sc.timer, 0, s);
     int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
     timer_end(sc.timer, 0, s);

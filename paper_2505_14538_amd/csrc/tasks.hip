@@ -324,6 +324,183 @@ void launch_order(const BinPtrs& b, hipStream_t s) {
                        b.order);
 }
 
+// Density lists built per group: the density tiles inside one gradient/
+// force tile (cells nest, so they are consecutive) share one cell search
+// over the group's box with the largest of their radii; each candidate is
+// then culled against every member's own box and radius, which gives each
+// member exactly the list its own search would give (in the group's search
+// order).  One wavefront per group runs the search twice: a counting pass
+// sizes the members' lists (allocated together from the bump counter), a
+// filling pass writes them.  The search is the costly part of a task build,
+// and groups are several times fewer than density tiles.
+struct GroupMem {
+    SearchMem sm;
+    int32_t lpre[LEAFCAP + 1];
+    float lo[WAVE][3], hi[WAVE][3];  // member boxes
+    float R[WAVE];                   // member radii
+    int32_t off[WAVE];               // member list offsets
+};
+
+template <typename T>
+__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Tile* __restrict__ tiles_d,
+                                                                 const int32_t* __restrict__ dfirst) {
+    __shared__ GroupMem smem_group[TASK_WPB];
+    const int wave = threadIdx.x / WAVE;
+    GroupMem& m = smem_group[wave];
+    const int lane = lane_id();
+    const int64_t np = (int64_t)*a.ntiles;
+    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
+    for (int64_t p = blockIdx.x * (int64_t)TASK_WPB + wave; p < np; p += nw) {
+        const Tile tp = a.tiles[p];
+        const int d0 = uniform(dfirst[p]);
+        int nd = uniform(dfirst[p + 1]) - d0;
+        if (nd > WAVE) nd = WAVE;  // a group has at most 64 particles
+        if (nd <= 0) continue;
+        const BoxInfo bi = a.boxtab[uniform(tp.box)];
+        const float L = (float)bi.L;
+        const float Rcap = 0.5f * L * (1.0f - 1e-6f);
+        // members: boxes, radii (from the largest h guess of each)
+        Tile tm;
+        if (lane < nd) {
+            tm = tiles_d[d0 + lane];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { m.lo[lane][d] = tm.lo[d]; m.hi[lane][d] = tm.hi[d]; }
+        }
+        const int pc = uniform(tp.count);
+        const int pb = uniform(tp.begin);
+        const T h = lane < pc ? a.hs[pb + lane] : (T)0;
+        float Rmax = 0.f;
+        for (int c = 0; c < nd; ++c) {
+            const int cb = __shfl(lane < nd ? tm.begin : 0, c, WAVE);
+            const int cc = __shfl(lane < nd ? tm.count : 0, c, WAVE);
+            const int s = pb + lane;
+            const T hm = wave_max(lane < pc && s >= cb && s < cb + cc ? h : (T)0);
+            float R = (float)(a.eps * hm * a.margin * (T)(1 + 4e-7));
+            if (!(R < Rcap)) {
+                if (a.margin == (T)1 && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
+                R = Rcap;
+            }
+            if (!(R > 0.f)) R = Rcap;
+            if (lane == 0) {
+                m.R[c] = R;
+                a.trad[d0 + c] = R;
+            }
+            Rmax = fmaxf(Rmax, R);
+        }
+        wave_sync();
+        // member c's squared radius, in lane c, formed as the loops form it
+        T R2c = (T)0;
+        if (lane < nd) {
+            const T Rt = (T)m.R[lane];
+            R2c = Rt * Rt;
+        }
+        TileGeom g;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { g.lo[d] = tp.lo[d]; g.hi[d] = tp.hi[d]; }
+        const T Lt = (T)bi.L;
+        const float R2p = Rmax * Rmax;
+        for (int pass = 0; pass < 2; ++pass) {
+            SearchState st;
+            search_init(m.sm, st, bi, g, Rmax);
+            int run = 0;  // lane c < nd: entries of member c so far
+            for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
+                const bool done = search_step<false>(m.sm, st, bi, g, R2p, a.cstart, a.hpyr,
+                                                     a.leaf_max, a.cnt);
+                if (st.nleaf > 0) {
+                    int c0 = lane < st.nleaf ? m.sm.lcnt[lane] : 0;
+                    int c1 = lane + WAVE < st.nleaf ? m.sm.lcnt[lane + WAVE] : 0;
+                    int tot0 = 0, tot1 = 0;
+                    const int e0 = wave_excl_scan(c0, tot0);
+                    const int e1 = wave_excl_scan(c1, tot1);
+                    m.lpre[lane] = e0;
+                    m.lpre[lane + WAVE] = tot0 + e1;
+                    if (lane == 0) m.lpre[2 * WAVE] = tot0 + tot1;
+                    wave_sync();
+                    const int nl = st.nleaf;
+                    const int nv = tot0 + tot1;
+                    for (int v0 = 0; v0 < nv; v0 += WAVE) {
+                        const int v = v0 + lane;
+                        T xs = 0, ys = 0, zs = 0;
+                        uint32_t ent = 0;
+                        const bool have = v < nv;
+                        if (have) {
+                            int lo = 0, hi = nl - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                            }
+                            int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
+                            if (j < 0 || j >= (int)a.n) j = 0;
+                            const int code = m.sm.lshift[lo];
+                            int sx, sy, sz;
+                            shift_of(code, sx, sy, sz);
+                            const V4<T> pa = a.pos4[j];
+                            xs = pa.x + (T)sx * Lt;
+                            ys = pa.y + (T)sy * Lt;
+                            zs = pa.z + (T)sz * Lt;
+                            ent = (uint32_t)j | ((uint32_t)code << 26);
+                        }
+                        for (int c = 0; c < nd; ++c) {
+                            const T r2c = __shfl(R2c, c, WAVE);
+                            const T gx = max((T)0, max((T)m.lo[c][0] - xs, xs - (T)m.hi[c][0]));
+                            const T gy = max((T)0, max((T)m.lo[c][1] - ys, ys - (T)m.hi[c][1]));
+                            const T gz = max((T)0, max((T)m.lo[c][2] - zs, zs - (T)m.hi[c][2]));
+                            const bool pass_c = have && dist2_unfused(gx, gy, gz) < r2c;
+                            const unsigned long long pm = ballot(pass_c);
+                            const int run_c = __shfl(run, c, WAVE);
+                            if (pass == 1 && pass_c) {
+                                const int64_t at = (int64_t)m.off[c] + run_c + mbcnt(pm);
+                                if (at < a.cand_cap) a.cands[at] = ent;
+                            }
+                            if (lane == c) run += __popcll(pm);
+                        }
+                    }
+                    st.nleaf = 0;
+                    wave_sync();
+                }
+                if (done) break;
+            }
+            if (pass == 0) {
+                // sizes -> one allocation for the group, offsets per member
+                int tot = 0;
+                const int e = wave_excl_scan(lane < nd ? run : 0, tot);
+                int64_t base = 0;
+                if (lane == 0) {
+                    base = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)tot);
+                    atomicAdd(&a.cnt->listed, (unsigned long long)tot);
+                }
+                base = __shfl(base, 0, WAVE);
+                const bool fits = base + tot <= a.cand_cap;
+                if (!fits && lane == 0) latch(a.cnt, SWSPH_ST_CAPACITY);
+                if (lane < nd) {
+                    m.off[lane] = (int32_t)(base + e);
+                    a.cand_off[d0 + lane] = fits ? (int32_t)(base + e) : -1;
+                    a.cand_cnt[d0 + lane] = fits ? run : 0;
+                    tiles_d[d0 + lane].cost = (float)tm.count * (float)run;
+                }
+                wave_sync();
+                if (!fits) break;
+            }
+        }
+        wave_sync();
+    }
+}
+
+template <typename T>
+static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin);
+
+// The first density task build with grouped searches (density tiles smaller
+// than the gradient/force tiles).
+template <typename T>
+void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s) {
+    if (bin.n <= 0) return;
+    const double margin = (sc.flags & SWSPH_FIXED_H) ? 1.0 : 1.25;
+    TArgs<T> a = targs<T>(bin, sc, margin);
+    launch_fill_u32(&bin.cnt->cand_used, 4, 0u, s);
+    hipLaunchKernelGGL(k_tasks_group<T>, dim3(wave_grid(bin.tile_cap, TASK_WPB)),
+                       dim3(TASK_WPB * WAVE), 0, s, a, bin.tiles_d, (const int32_t*)bin.dfirst);
+}
+
 template <typename T>
 static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     TArgs<T> a;
@@ -365,6 +542,8 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     hipLaunchKernelGGL(kovf, dim3(wave_grid(1024, TASK_WPB)), block, 0, s, a, (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
+template void launch_tasks_grouped<float>(const BinPtrs&, const Scheme&, hipStream_t);
+template void launch_tasks_grouped<double>(const BinPtrs&, const Scheme&, hipStream_t);
 template void launch_tasks<float>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
 template void launch_tasks<double>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
 
