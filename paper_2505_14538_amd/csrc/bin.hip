@@ -441,10 +441,12 @@ void launch_make_tiles(const BinPtrs& b, hipStream_t s) {
     if (b.tiles_d != b.tiles) {
         make_tile_set<T>(b, b.tile_d, b.tiles_d, b.order_d, &b.cnt->n_tiles_d, s);
         make_tile_set<T>(b, b.tile, b.tiles, b.order, &b.cnt->n_tiles, s);
-        hipLaunchKernelGGL(k_dgroups, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
-                           (const Tile*)b.tiles_d, (const unsigned long long*)&b.cnt->n_tiles_d,
-                           (const unsigned long long*)&b.cnt->n_tiles, (const int32_t*)b.slot,
-                           (const int32_t*)b.tmpidx, b.dfirst);
+        // groups need density tiles inside gradient/force tiles: smaller ones
+        if (b.tile_d < b.tile)
+            hipLaunchKernelGGL(k_dgroups, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
+                               (const Tile*)b.tiles_d, (const unsigned long long*)&b.cnt->n_tiles_d,
+                               (const unsigned long long*)&b.cnt->n_tiles, (const int32_t*)b.slot,
+                               (const int32_t*)b.tmpidx, b.dfirst);
     } else {
         make_tile_set<T>(b, b.tile, b.tiles, b.order, &b.cnt->n_tiles, s);
         launch_copy_u64(&b.cnt->n_tiles_d, &b.cnt->n_tiles, s);

@@ -472,7 +472,7 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.d_out;
     a.iout = b.d_int;
-    if (bin.tiles_d != bin.tiles) {
+    if (bin.tile_d < bin.tile) {
         launch_tasks_grouped<T>(bin, sc, s);  // one search per gradient/force tile
         if (sc.order == 0) launch_order(b, s);
     } else {
@@ -562,27 +562,51 @@ template void launch_prep_dens<double>(const BinPtrs&, const Scheme&, const swsp
                                        hipStream_t);
 
 // Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
-// of every box: fine cells by atomic max over particles, then each fine cell
-// pushes its value up while it raises the parent.
-// Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
-// of every box: each particle raises its fine cell and walks up while it
-// raises the parent (most walks stop after a level or two).
+// of every box.  Particles are in Morton order, so the particles of a cell
+// at any level are consecutive: per level, a wavefront takes the maximum
+// over each run of lanes in the same cell (segmented scan with lane
+// shuffles) and only the last lane of a run raises the cell (atomic max,
+// skipped when the cell already holds as much).
 template <typename T>
 __global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
                        const uint32_t* __restrict__ keys, int32_t n_box,
                        const BoxInfo* __restrict__ boxtab, const T* __restrict__ hs, T eps,
                        float* __restrict__ pyr) {
-    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int32_t p = perm[s];
-    const BoxInfo bi = boxtab[box_of_sorted(s, n_box, boxtab)];
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool have = s < n;
+    const int lane = lane_id();
+    int b = 0;
+    uint32_t mort = 0;
+    float H = 0.f;
+    if (have) {
+        b = box_of_sorted(s, n_box, boxtab);
+        mort = keys[perm[s]] - (uint32_t)boxtab[b].fine_off;
+        H = (float)(eps * hs[s]) * (1.0f + 1e-6f);
+    }
+    const BoxInfo bi = boxtab[b];
     const int k = bi.k < 10 ? bi.k : 10;
-    const uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
-    const float H = (float)(eps * hs[s]) * (1.0f + 1e-6f);
-    for (int l = k; l >= 0; --l) {
-        float* c = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
-        if (*c >= H) break;
-        atomicMax((int*)c, __float_as_int(H));
+    // all lanes run every level of the deepest box in the wavefront
+    const int kmax = wave_max(have ? k : 0);
+    for (int up = 0; up <= kmax; ++up) {
+        const int l = k - up;
+        // cell id at this level; lanes past their box's root or without a
+        // particle get ids no other lane has
+        const uint64_t cell = (have && l >= 0)
+            ? ((uint64_t)b << 32) | (uint64_t)(mort >> (3 * (k - l)))
+            : ~(uint64_t)lane;
+        float v = H;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const float w = __shfl_up(v, o, WAVE);
+            const uint64_t c = __shfl_up(cell, o, WAVE);
+            if (lane >= o && c == cell) v = fmaxf(v, w);
+        }
+        const uint64_t next = __shfl_down(cell, 1, WAVE);
+        const bool tail = lane == WAVE - 1 || next != cell;
+        if (have && l >= 0 && tail) {
+            float* c = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
+            if (*c < v) atomicMax((int*)c, __float_as_int(v));
+        }
     }
 }
 

@@ -103,11 +103,12 @@ def test_many_boxes_full_size(S, oracle_mod):
 
 
 def test_ragged_small_and_tiles(S, oracle_mod):
-    """A set whose size is no multiple of any tile, for every tile size."""
+    """A set whose size is no multiple of any tile, for every tile size, with
+    density tiles equal to, smaller and larger than the other loops' tiles."""
     O = oracle_mod
     p = W.tiny(nside=11)
-    for tile in (8, 16, 32, 64):
-        d, g, f, st = gpu_all(S, p, tile=tile, tile_dens=tile)
+    for tile, td in ((8, 8), (16, 16), (32, 32), (64, 64), (64, 8), (16, 64)):
+        d, g, f, st = gpu_all(S, p, tile=tile, tile_dens=td)
         assert st["code"] == 0, st
         check_sample(O, p, d, g, f, np.arange(p.n))
 
