@@ -159,13 +159,28 @@ template <typename T> __device__ __forceinline__ int32_t as_int(T v);
 template <> __device__ __forceinline__ int32_t as_int<float>(float v) { return __float_as_int(v); }
 template <> __device__ __forceinline__ int32_t as_int<double>(double v) { return (int32_t)v; }
 
-// Stream tile t's candidate list through the lanes (coalesced entries,
-// gathers of the j-data), cull against the tile box (radius R, or the
-// j-particle's own support for the symmetric loops; the list was culled with
-// the build radius already, so this only matters when the caller passes a
-// smaller R), stage survivors in LDS; flush(nsurv) is called whenever the
-// buffer could overflow (the buffer is empty afterwards).  Returns the
-// number of staged survivors left for the caller.
+// The j-data a loop stages, gathered for one candidate in one go.
+template <int LK, typename T> struct JData {
+    V4<T> p, v, d, x;  // pos4 (x, y, z, m), vel4, dens4 (rho, f, c, A), aux4 (adjoint)
+    T h;
+};
+template <int LK, typename T>
+__device__ __forceinline__ void gather_j(const KArgs<T>& a, int j, JData<LK, T>& r) {
+    r.p = a.pos4[j];
+    if (LK <= L_ADJA) r.v = a.vel4[j];
+    if (LK == L_GRAD || LK == L_FORCE || LK == L_ADJA) r.d = a.dens4[j];
+    if (LK >= L_ADJA) r.x = a.aux4[j];
+    if (Symmetric<LK>::value) r.h = a.hs[j];
+}
+
+// Stream tile t's candidate list through the lanes and stage it in LDS.
+// Per batch of 64 candidates the entries (read one batch ahead) give the
+// j-particles, and every field the loop needs is gathered at once, so a
+// batch costs one memory round trip; the list was culled at build time, so
+// the cull here (radius R; for the symmetric loops also the j-particle's own
+// support) only matters when the caller passes a smaller R.  flush(nsurv) is
+// called whenever the buffer could overflow (the buffer is empty
+// afterwards).  Returns the number of staged survivors left for the caller.
 template <int LK, typename T, int CAP, class WM, class Flush>
 __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
                           T R2, int& flushes, Flush&& flush) {
@@ -177,34 +192,35 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
     const T L = (T)bi.L;
     int nsurv = 0;
     flushes = 0;
+    uint32_t e_next = lane < nc ? a.cands[off + lane] : 0u;
     for (int64_t base = 0; base < nc; base += WAVE) {
+        const bool have = base + lane < nc;
+        const uint32_t e = e_next;
+        int j = (int)(e & 0x3ffffffu);
+        if (j >= a.n) j = 0;  // cannot happen with a valid list
+        JData<LK, T> r;
+        if (have) gather_j<LK, T>(a, j, r);
+        if (base + WAVE + lane < nc) e_next = a.cands[off + base + WAVE + lane];
         if (nsurv + WAVE > CAP) {
             flush(nsurv);
             nsurv = 0;
             ++flushes;
         }
-        const int64_t v = base + lane;
         bool pass = false;
-        V4<T> pa;
         T xs = 0, ys = 0, zs = 0;
-        int j = 0;
-        if (v < nc) {
-            const uint32_t e = a.cands[off + v];
-            j = (int)(e & 0x3ffffffu);
-            if (j >= a.n) j = 0;  // cannot happen with a valid list
+        if (have) {
             int sx, sy, sz;
             shift_of((int)(e >> 26), sx, sy, sz);
-            pa = a.pos4[j];
-            xs = pa.x + (T)sx * L;
-            ys = pa.y + (T)sy * L;
-            zs = pa.z + (T)sz * L;
+            xs = r.p.x + (T)sx * L;
+            ys = r.p.y + (T)sy * L;
+            zs = r.p.z + (T)sz * L;
             const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
             const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
             const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
             const T d2 = dist2_unfused(gx, gy, gz);
             T crit = R2;
             if (Symmetric<LK>::value) {
-                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                const T Hj = mul_unfused(a.eps, r.h);
                 crit = max(crit, mul_unfused(Hj, Hj));
             }
             pass = d2 < crit;
@@ -212,26 +228,26 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
         const unsigned long long pm = ballot(pass);
         if (pass) {
             const int k = nsurv + mbcnt(pm);
-            const V4<T> va = a.vel4[j];
+            const V4<T> pa = r.p, va = r.v;
             if (LK == L_DENS) {
                 m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
             } else if (LK == L_GRAD) {
-                const V4<T> da = a.dens4[j];  // (rho, f, c, A)
+                const V4<T> da = r.d;  // (rho, f, c, A)
                 m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
                 m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
             } else if (LK == L_FORCE) {
-                const V4<T> da = a.dens4[j];
-                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                const V4<T> da = r.d;
+                const T Hj = mul_unfused(a.eps, r.h);
                 m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
                 m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
                 m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
             } else if (LK == L_ADJA) {
-                const V4<T> da = a.dens4[j];   // (rho, f, c, A)
-                const V4<T> wj = a.aux4[j];    // (dL/dax, dL/day, dL/daz, dL/ddu)
-                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                const V4<T> da = r.d;   // (rho, f, c, A)
+                const V4<T> wj = r.x;   // (dL/dax, dL/day, dL/daz, dL/ddu)
+                const T Hj = mul_unfused(a.eps, r.h);
                 m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
                 m.s[2][k] = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
@@ -239,9 +255,9 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
                 m.s[4][k] = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
             } else {
                 // density adjoint: (m, rho_bar, rho'_bar, 1/H); implicit h: (lambda h^3, 1/H, idx, 0)
-                const T Hj = mul_unfused(a.eps, a.hs[j]);
+                const T Hj = mul_unfused(a.eps, r.h);
                 m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                m.s[1][k] = a.aux4[j];
+                m.s[1][k] = r.x;
             }
         }
         nsurv += __popcll(pm);
@@ -324,12 +340,12 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
 //  * queue: every wavefront pops QCHUNK consecutive tasks at a time until the
 //    list is drained (at most tile_cap + 1 pops per list).  With xcd_split
 //    the list (in Morton order) is cut into NXCD contiguous segments and a
-//    workgroup starts on the segment of its XCD (workgroups are dealt to the
-//    XCDs round-robin), so each XCD's L2 cache sees a compact region of the
-//    box; a wavefront whose segment is drained helps the next ones.
+//    wavefront starts on the segment of the XCD it runs on (hardware XCC
+//    id), so each XCD's L2 cache sees a compact region of the box; a
+//    wavefront whose segment is drained helps the next ones.
 //  * flat: the static round-robin schedule.
 //  * per-task: the one task of the launch.
-constexpr int QCHUNK = 4;
+constexpr int QCHUNK = 2;
 constexpr int NXCD = 8;
 
 template <class Run>
@@ -351,7 +367,7 @@ __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&&
     const int64_t nt = (int64_t)*a.ntask;
     if (mode == MODE_QUEUE) {
         if (a.xcd_split) {
-            const int x0 = blockIdx.x % NXCD;
+            const int x0 = xcc_id() % NXCD;
             for (int y = 0; y < NXCD; ++y) {
                 const int x = (x0 + y) % NXCD;
                 pop_segment(&a.queue[x], nt * x / NXCD, nt * (x + 1) / NXCD, a.tile_cap, a.order,

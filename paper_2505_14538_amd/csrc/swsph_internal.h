@@ -113,6 +113,12 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// XCD (accelerator complex die) the wavefront runs on: the hardware XCC_ID
+// register (read only).
+__device__ __forceinline__ int xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;  // hwreg(XCC_ID, 0, 4)
+}
+
 __device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ __forceinline__ double shfl_xor(double v, int m) { return __shfl_xor(v, m, WAVE); }
 __device__ __forceinline__ int shfl_xor(int v, int m) { return __shfl_xor(v, m, WAVE); }
