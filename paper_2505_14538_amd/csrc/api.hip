@@ -141,7 +141,6 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.cand_cnt = take(4 * (uint64_t)(toff + 1));
     l.cand_off = take(4 * (uint64_t)(toff + 2));
-    l.ovf = take(4 * (uint64_t)toff);
     G.cand_cap = cand_capacity(n);
     l.cands = take(4 * (uint64_t)G.cand_cap);
     l.trad = take(4 * (uint64_t)toff);
@@ -304,7 +303,6 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.ord_base = (int32_t*)(w + l.ord_base);
     b.cand_cnt = (int32_t*)(w + l.cand_cnt);
     b.cand_off = (int32_t*)(w + l.cand_off);
-    b.ovf = (int32_t*)(w + l.ovf);
     b.cands = (uint32_t*)(w + l.cands);
     b.cand_cap = pl->G.cand_cap;
     b.trad = (float*)(w + l.trad);

@@ -39,7 +39,6 @@ struct BinPtrs {
     int32_t* dfirst;           // first density tile of each gradient/force tile (+ end)
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *cand_cnt, *cand_off;
-    int32_t* ovf;
     uint32_t* cands;
     int64_t cand_cap;
     float* trad;

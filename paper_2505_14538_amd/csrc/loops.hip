@@ -26,7 +26,7 @@ namespace swsph {
 // ------------------------------------------------------------ density tile
 
 template <typename T, int CAP>
-__device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
+__device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, WaveStats& ws) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
@@ -211,25 +211,23 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t) {
             if (!(Rn < Rcap)) Rn = Rcap;
             a.trad[t] = (float)Rn;
             a.tflag[t] = 1;
-            atomicAdd(&a.cnt->restages, 1ull);
         } else {
             a.tflag[t] = 0;
         }
-        atomicAdd(&a.cnt->pairs_tested[0], tested * (unsigned long long)tl.count);
-        atomicAdd(&a.cnt->pairs_inside[0], ins);
-        atomicAdd(&a.cnt->newton_sweeps, (unsigned long long)(iters - iters0));
-        atomicMax(&a.cnt->newton_max, (unsigned long long)iters);
-        if (fmask) {
-            atomicAdd(&a.cnt->newton_failed, (unsigned long long)__popcll(fmask));
-            latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
-        }
+        if (fmask) latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
     }
+    ws.restages += pmask ? 1ull : 0ull;
+    ws.tested += tested * (unsigned long long)tl.count;
+    ws.inside += ins;
+    ws.sweeps += (unsigned long long)(iters - iters0);
+    ws.smax = max(ws.smax, (unsigned long long)wave_max(iters));
+    ws.failed += (unsigned long long)__popcll(fmask);
 }
 
 // ----------------------------------------------------------- gradient tile
 
 template <typename T, int CAP>
-__device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
+__device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t, WaveStats& ws) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
@@ -294,17 +292,14 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t) {
         a.out[0 * a.n + i] = vsig;
         a.out[1 * a.n + i] = (T)2 * k5 * lap;
     }
-    const unsigned long long ins = (unsigned long long)wave_sum(lead ? inside : 0);
-    if (lane == 0) {
-        atomicAdd(&a.cnt->pairs_tested[1], tested * (unsigned long long)tl.count);
-        atomicAdd(&a.cnt->pairs_inside[1], ins);
-    }
+    ws.inside += (unsigned long long)wave_sum(lead ? inside : 0);
+    ws.tested += tested * (unsigned long long)tl.count;
 }
 
 // -------------------------------------------------------------- force tile
 
 template <typename T, int CAP>
-__device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
+__device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, WaveStats& ws) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
@@ -394,20 +389,17 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t) {
         a.out[3 * a.n + i] = du;
         a.iout[i] = nint;
     }
-    const unsigned long long ins = (unsigned long long)wave_sum(lead ? nint : 0);
-    if (lane == 0) {
-        atomicAdd(&a.cnt->pairs_tested[2], tested * (unsigned long long)tl.count);
-        atomicAdd(&a.cnt->pairs_inside[2], ins);
-    }
+    ws.inside += (unsigned long long)wave_sum(lead ? nint : 0);
+    ws.tested += tested * (unsigned long long)tl.count;
 }
 
 // ----------------------------------------------------------------- drivers
 
 template <int LK, typename T, int CAP>
-__device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t) {
-    if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t);
-    else if (LK == L_GRAD) gradient_tile<T, CAP>(*(WaveMem<T, CAP, 3>*)wm, a, t);
-    else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t);
+__device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, WaveStats& ws) {
+    if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t, ws);
+    else if (LK == L_GRAD) gradient_tile<T, CAP>(*(WaveMem<T, CAP, 3>*)wm, a, t, ws);
+    else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
 template <int LK, typename T, int CAP>
@@ -416,7 +408,9 @@ __global__ void __launch_bounds__(WPB * WAVE) k_loop(KArgs<T> a, int mode) {
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
     const int wave = threadIdx.x / WAVE;
     char* wm = smem + wave * WMS;
-    for_each_task(a, mode, [&](int t) { run_tile<LK, T, CAP>(wm, a, t); });
+    WaveStats ws;
+    for_each_task(a, mode, [&](int t) { run_tile<LK, T, CAP>(wm, a, t, ws); });
+    ws.flush(a.cnt, LK);
 }
 
 int device_cu_count() {

@@ -336,6 +336,23 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     return a;
 }
 
+// Statistics a wavefront gathers over its tiles (uniform values; added to
+// the device counters once per wavefront at the end of a launch, not per
+// tile, so hundreds of thousands of small tiles do not queue on a few
+// atomic counters).
+struct WaveStats {
+    unsigned long long tested = 0, inside = 0, sweeps = 0, smax = 0, failed = 0, restages = 0;
+    __device__ void flush(Counters* c, int loop) const {
+        if (lane_id() != 0) return;
+        if (tested) atomicAdd(&c->pairs_tested[loop], tested);
+        if (inside) atomicAdd(&c->pairs_inside[loop], inside);
+        if (sweeps) atomicAdd(&c->newton_sweeps, sweeps);
+        if (smax) atomicMax(&c->newton_max, smax);
+        if (failed) atomicAdd(&c->newton_failed, failed);
+        if (restages) atomicAdd(&c->restages, restages);
+    }
+};
+
 // Task dispatch inside a loop kernel.
 //  * queue: every wavefront pops QCHUNK consecutive tasks at a time until the
 //    list is drained (at most tile_cap + 1 pops per list).  With xcd_split

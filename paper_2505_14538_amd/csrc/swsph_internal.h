@@ -60,8 +60,7 @@ struct Counters {
     unsigned long long n_tiles_d;      // tiles of the density loop
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
     unsigned long long cand_used;      // task-list entries taken by the current build
-    unsigned long long n_ovf;          // tiles of the current build whose list overflowed LDS
-    unsigned long long reserved[4];
+    unsigned long long reserved[5];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };
@@ -74,7 +73,7 @@ struct Layout {
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
     uint64_t tiles, order, tiles_d, order_d, dfirst, ord_table, ord_base;
     // task lists (CSR of cells per tile) and density fix-up state
-    uint64_t cand_cnt, cand_off, cands, trad, tflag, ovf;
+    uint64_t cand_cnt, cand_off, cands, trad, tflag;
     // sorted-order results
     uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
     uint64_t d_int;     // 2 arrays of int32: nngb iters

@@ -28,7 +28,6 @@ struct TArgs {
     int64_t cand_cap;
     float* trad;
     const int32_t* tflag;
-    int32_t* ovf;               // tiles whose list overflowed the LDS buffer
     Counters* cnt;
     T eps;
     T margin;
@@ -42,12 +41,11 @@ struct TArgs {
 // below the loop's radius R (force: below max(R, H_j), the symmetric
 // support) -- as entries j | image << 26 (periodic image code, see
 // search.h).  The cull is done once here, so the loops only gather.
-// Main pass: a tile's entries collect in LDS (up to TASK_BUF) and are copied
-// to space taken from a device bump counter, so each list is contiguous; the
-// tile's radius and cost (particles x candidates) are recorded.  A longer
-// list is only counted and put on the overflow list; the overflow pass takes
-// exactly that much space and runs the search again, writing straight to
-// global memory.  Wavefront-uniform.
+// The entries collect in LDS (up to TASK_BUF) and are copied to space taken
+// from a device bump counter, so each list is contiguous; a longer list is
+// counted, given exactly that much space, and the search runs again writing
+// straight to global memory.  The tile's radius and cost (particles x
+// candidates) are recorded.  Wavefront-uniform.
 #ifndef SWSPH_TASK_BUF
 #define SWSPH_TASK_BUF 2048
 #endif
@@ -60,14 +58,13 @@ struct TaskMem {
 };
 
 template <typename T, int MODE>
-__device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t,
-                         bool overflow_pass, int fixup, int64_t base) {
+__device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t, int fixup) {
     const int lane = lane_id();
     const BoxInfo bi = a.boxtab[tl.box];
     const float L = (float)bi.L;
     const float Rcap = 0.5f * L * (1.0f - 1e-6f);
     float R;
-    if (overflow_pass || (MODE == 0 && fixup)) {
+    if (MODE == 0 && fixup) {
         R = a.trad[t];
     } else {
         const bool act = lane < tl.count;
@@ -88,98 +85,102 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
     for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
     float Rstart = R;
     if (MODE == 2) Rstart = fmaxf(R, a.hpyr[bi.pyr_off]);
-    SearchState st;
-    search_init(m.sm, st, bi, g, Rstart);
     const float R2 = R * R;
     const T Rt = (T)R;
     const T R2t = Rt * Rt;  // the loops cull with the same value
     const T Lt = (T)bi.L;
-    int64_t total = 0;
-    const int64_t mine = overflow_pass ? (int64_t)a.cand_cnt[t] : 0;
-    for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
-        const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr,
-                                                 a.leaf_max, a.cnt);
-        if (st.nleaf > 0) {
-            // prefix sums of the batch's particle counts (two lanes' worth each)
-            int c0 = lane < st.nleaf ? m.sm.lcnt[lane] : 0;
-            int c1 = lane + WAVE < st.nleaf ? m.sm.lcnt[lane + WAVE] : 0;
-            int tot0 = 0, tot1 = 0;
-            const int e0 = wave_excl_scan(c0, tot0);
-            const int e1 = wave_excl_scan(c1, tot1);
-            m.lpre[lane] = e0;
-            m.lpre[lane + WAVE] = tot0 + e1;
-            if (lane == 0) m.lpre[2 * WAVE] = tot0 + tot1;
-            wave_sync();
-            const int nl = st.nleaf;
-            const int nv = tot0 + tot1;
-            for (int v0 = 0; v0 < nv; v0 += WAVE) {
-                const int v = v0 + lane;
-                bool pass = false;
-                uint32_t ent = 0;
-                if (v < nv) {
-                    int lo = 0, hi = nl - 1;
-                    while (lo < hi) {  // last leaf whose prefix is <= v
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+    bool direct = false;    // second round: write to global memory at base
+    int64_t base = 0, known = 0;
+    for (int round = 0; round < 2; ++round) {
+        SearchState st;
+        search_init(m.sm, st, bi, g, Rstart);
+        int64_t total = 0;
+        for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
+            const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr,
+                                                     a.leaf_max, a.cnt);
+            if (st.nleaf > 0) {
+                // prefix sums of the batch's particle counts (two lanes' worth each)
+                int c0 = lane < st.nleaf ? m.sm.lcnt[lane] : 0;
+                int c1 = lane + WAVE < st.nleaf ? m.sm.lcnt[lane + WAVE] : 0;
+                int tot0 = 0, tot1 = 0;
+                const int e0 = wave_excl_scan(c0, tot0);
+                const int e1 = wave_excl_scan(c1, tot1);
+                m.lpre[lane] = e0;
+                m.lpre[lane + WAVE] = tot0 + e1;
+                if (lane == 0) m.lpre[2 * WAVE] = tot0 + tot1;
+                wave_sync();
+                const int nl = st.nleaf;
+                const int nv = tot0 + tot1;
+                for (int v0 = 0; v0 < nv; v0 += WAVE) {
+                    const int v = v0 + lane;
+                    bool pass = false;
+                    uint32_t ent = 0;
+                    if (v < nv) {
+                        int lo = 0, hi = nl - 1;
+                        while (lo < hi) {  // last leaf whose prefix is <= v
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                        }
+                        int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
+                        if (j < 0 || j >= (int)a.n) j = 0;  // cannot happen with a valid cell table
+                        const int code = m.sm.lshift[lo];
+                        int sx, sy, sz;
+                        shift_of(code, sx, sy, sz);
+                        const V4<T> pa = a.pos4[j];
+                        const T xs = pa.x + (T)sx * Lt, ys = pa.y + (T)sy * Lt, zs = pa.z + (T)sz * Lt;
+                        const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+                        const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+                        const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+                        const T d2 = dist2_unfused(gx, gy, gz);
+                        T crit = R2t;
+                        if (MODE == 2) {
+                            const T Hj = mul_unfused(a.eps, a.hs[j]);
+                            crit = max(crit, mul_unfused(Hj, Hj));
+                        }
+                        pass = d2 < crit;
+                        ent = (uint32_t)j | ((uint32_t)code << 26);
                     }
-                    int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
-                    if (j < 0 || j >= (int)a.n) j = 0;  // cannot happen with a valid cell table
-                    const int code = m.sm.lshift[lo];
-                    int sx, sy, sz;
-                    shift_of(code, sx, sy, sz);
-                    const V4<T> pa = a.pos4[j];
-                    const T xs = pa.x + (T)sx * Lt, ys = pa.y + (T)sy * Lt, zs = pa.z + (T)sz * Lt;
-                    const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
-                    const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
-                    const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
-                    const T d2 = dist2_unfused(gx, gy, gz);
-                    T crit = R2t;
-                    if (MODE == 2) {
-                        const T Hj = mul_unfused(a.eps, a.hs[j]);
-                        crit = max(crit, mul_unfused(Hj, Hj));
+                    const unsigned long long pm = ballot(pass);
+                    if (pass) {
+                        const int64_t at = total + mbcnt(pm);
+                        if (direct) {
+                            if (at < known) a.cands[base + at] = ent;
+                        } else if (at < TASK_BUF) {
+                            m.buf[at] = ent;
+                        }
                     }
-                    pass = d2 < crit;
-                    ent = (uint32_t)j | ((uint32_t)code << 26);
+                    total += __popcll(pm);
                 }
-                const unsigned long long pm = ballot(pass);
-                if (pass) {
-                    const int64_t at = total + mbcnt(pm);
-                    if (overflow_pass) {
-                        if (at < mine && base + at < a.cand_cap) a.cands[base + at] = ent;
-                    } else if (at < TASK_BUF) {
-                        m.buf[at] = ent;
-                    }
-                }
-                total += __popcll(pm);
+                st.nleaf = 0;
+                wave_sync();
             }
-            st.nleaf = 0;
-            wave_sync();
+            if (done) break;
         }
-        if (done) break;
-    }
-    if (!overflow_pass) {
+        if (direct) break;
+        // first round: record, allocate, copy (or go round again)
         int64_t at = 0;
         if (lane == 0) {
-            a.cand_cnt[t] = (int32_t)total;
             a.tiles[t].cost = (float)tl.count * (float)total;
             atomicAdd(&a.cnt->listed, (unsigned long long)total);
-            if (total > TASK_BUF) {
-                a.cand_off[t] = -1;
-                a.ovf[atomicAdd(&a.cnt->n_ovf, 1ull)] = (int32_t)t;
-            } else {
-                at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
-                a.cand_off[t] = at + total <= a.cand_cap ? (int32_t)at : -1;
-                if (at + total > a.cand_cap) {
-                    a.cand_cnt[t] = 0;
-                    latch(a.cnt, SWSPH_ST_CAPACITY);
-                }
+            at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
+            const bool fits = at + total <= a.cand_cap;
+            a.cand_off[t] = fits ? (int32_t)at : -1;
+            a.cand_cnt[t] = fits ? (int32_t)total : 0;
+            if (!fits) {
+                latch(a.cnt, SWSPH_ST_CAPACITY);
+                at = -1;
             }
         }
         at = __shfl(at, 0, WAVE);
-        if (total <= TASK_BUF && at + total <= a.cand_cap)
+        if (at < 0) break;
+        if (total <= TASK_BUF) {
             for (int k = lane; k < total; k += WAVE) a.cands[at + k] = m.buf[k];
-    } else if (lane == 0 && base + total > a.cand_cap) {
-        latch(a.cnt, SWSPH_ST_CAPACITY);
+            break;
+        }
+        direct = true;
+        base = at;
+        known = total;
+        wave_sync();
     }
     wave_sync();
 }
@@ -207,38 +208,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
             }
             continue;
         }
-        task_one<T, MODE>(a, m, tl, t, false, fixup, 0);
-    }
-}
-
-// Tiles whose list did not fit the LDS buffer: space of the counted size,
-// then the search again.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_ovf(TArgs<T> a, int fixup) {
-    __shared__ TaskMem smem_task[TASK_WPB];
-    const int wave = threadIdx.x / WAVE;
-    TaskMem& m = smem_task[wave];
-    const int64_t no = (int64_t)a.cnt->n_ovf;
-    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
-    for (int64_t q = blockIdx.x * (int64_t)TASK_WPB + wave; q < no; q += nw) {
-        const int64_t t = a.ovf[q];
-        Tile tl = a.tiles[t];
-        tl.count = uniform(tl.count);
-        tl.box = uniform(tl.box);
-        int64_t at = 0;
-        if (lane_id() == 0) {
-            const int64_t c = a.cand_cnt[t];
-            at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)c);
-            if (at + c > a.cand_cap) {
-                a.cand_cnt[t] = 0;
-                latch(a.cnt, SWSPH_ST_CAPACITY);
-                at = -1;
-            }
-            a.cand_off[t] = (int32_t)at;
-        }
-        at = __shfl(at, 0, WAVE);
-        if (at < 0) continue;
-        task_one<T, MODE>(a, m, tl, t, true, fixup, at);
+        task_one<T, MODE>(a, m, tl, t, fixup);
     }
 }
 
@@ -496,7 +466,7 @@ void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s) {
     if (bin.n <= 0) return;
     const double margin = (sc.flags & SWSPH_FIXED_H) ? 1.0 : 1.25;
     TArgs<T> a = targs<T>(bin, sc, margin);
-    launch_fill_u32(&bin.cnt->cand_used, 4, 0u, s);
+    launch_fill_u32(&bin.cnt->cand_used, 2, 0u, s);
     hipLaunchKernelGGL(k_tasks_group<T>, dim3(wave_grid(bin.tile_cap, TASK_WPB)),
                        dim3(TASK_WPB * WAVE), 0, s, a, bin.tiles_d, (const int32_t*)bin.dfirst);
 }
@@ -517,7 +487,6 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.cand_cap = b.cand_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
-    a.ovf = b.ovf;
     a.cnt = b.cnt;
     a.eps = (T)sc.eps;
     a.margin = (T)margin;
@@ -535,11 +504,8 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     const dim3 block(TASK_WPB * WAVE);
     void (*kern)(TArgs<T>, int) =
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
-    void (*kovf)(TArgs<T>, int) =
-        mode == 0 ? k_tasks_ovf<T, 0> : (mode == 1 ? k_tasks_ovf<T, 1> : k_tasks_ovf<T, 2>);
-    launch_fill_u32(&b.cnt->cand_used, 4, 0u, s);  // cand_used and n_ovf
+    launch_fill_u32(&b.cnt->cand_used, 2, 0u, s);
     hipLaunchKernelGGL(kern, dim3(wave_grid(b.tile_cap, TASK_WPB)), block, 0, s, a, (int)fixup);
-    hipLaunchKernelGGL(kovf, dim3(wave_grid(1024, TASK_WPB)), block, 0, s, a, (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
 template void launch_tasks_grouped<float>(const BinPtrs&, const Scheme&, hipStream_t);
