@@ -516,67 +516,66 @@ int swsph_density(swsph_plan* pl, const swsph_particles* p, swsph_density_out* o
     return hip_check(hipGetLastError(), "density");
 }
 
-int swsph_gradient(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
-                   swsph_gradient_out* o, void* ws, void* stream) {
-    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
-    int r = check_particles(pl, p, true);
-    if (r) return r;
-    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
-        return fail(SWSPH_E_ARG, "gradient needs density h, rho and f");
-    if (!o) return fail(SWSPH_E_ARG, "gradient output is NULL");
-    r = check_bound(pl, p, ws);
-    if (r) return r;
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// Gradient and/or force over one density result: the density fields are
+// gathered into binned order and the task lists built once for both loops.
+template <typename T>
+int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, hipStream_t s) {
     BinPtrs b = ptrs_of(pl, ws);
     Scheme sc = scheme_of(pl);
     const int mode = mode_of(pl);
     const int64_t n = b.n;
-    if (pl->cfg.dtype == SWSPH_F64) {
-        launch_prep_dens<double>(b, sc, d, s);
-        r = launch_gradient<double>(b, sc, mode, pl->lds_cap, s);
-        launch_unsort<double>(n, b.rank, (double*)b.g_out, o->v_sig, s);
-        launch_unsort<double>(n, b.rank, (double*)b.g_out + n, o->lap_u, s);
-    } else {
-        launch_prep_dens<float>(b, sc, d, s);
-        r = launch_gradient<float>(b, sc, mode, pl->lds_cap, s);
-        launch_unsort<float>(n, b.rank, (float*)b.g_out, o->v_sig, s);
-        launch_unsort<float>(n, b.rank, (float*)b.g_out + n, o->lap_u, s);
+    (void)p;
+    launch_prep_dens<T>(b, sc, d, s);
+    launch_gf_tasks<T>(b, sc, s);
+    if (go) {
+        if (launch_gradient<T>(b, sc, mode, pl->lds_cap, s))
+            return fail(SWSPH_E_HIP, "gradient kernel launch failed");
+        launch_unsort<T>(n, b.rank, (T*)b.g_out, go->v_sig, s);
+        launch_unsort<T>(n, b.rank, (T*)b.g_out + n, go->lap_u, s);
     }
-    if (r) return fail(SWSPH_E_HIP, "gradient kernel launch failed");
-    return hip_check(hipGetLastError(), "gradient");
+    if (fo) {
+        if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
+            return fail(SWSPH_E_HIP, "force kernel launch failed");
+        void* dst[4] = {fo->ax, fo->ay, fo->az, fo->dudt};
+        for (int k = 0; k < 4; ++k) launch_unsort<T>(n, b.rank, (T*)b.f_out + k * n, dst[k], s);
+        if (fo->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, fo->nint, s);
+    }
+    return hip_check(hipGetLastError(), go ? (fo ? "gradient+force" : "gradient") : "force");
+}
+
+int gf_checked(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
+        return fail(SWSPH_E_ARG, "gradient and force need density h, rho and f");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    return pl->cfg.dtype == SWSPH_F64 ? gf_enqueue<double>(pl, p, d, go, fo, ws, s)
+                                      : gf_enqueue<float>(pl, p, d, go, fo, ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int swsph_gradient(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                   swsph_gradient_out* o, void* ws, void* stream) {
+    if (pl && !o) return fail(SWSPH_E_ARG, "gradient output is NULL");
+    return gf_checked(pl, p, d, o, nullptr, ws, stream);
 }
 
 int swsph_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
                 swsph_force_out* o, void* ws, void* stream) {
-    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
-    int r = check_particles(pl, p, true);
-    if (r) return r;
-    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
-        return fail(SWSPH_E_ARG, "force needs density h, rho and f");
-    if (!o) return fail(SWSPH_E_ARG, "force output is NULL");
-    r = check_bound(pl, p, ws);
-    if (r) return r;
-    hipStream_t s = (hipStream_t)stream;
-    BinPtrs b = ptrs_of(pl, ws);
-    Scheme sc = scheme_of(pl);
-    const int mode = mode_of(pl);
-    const int64_t n = b.n;
-    if (pl->cfg.dtype == SWSPH_F64) {
-        launch_prep_dens<double>(b, sc, d, s);
-        launch_hmax_pyramid<double>(b, sc, s);
-        r = launch_force<double>(b, sc, mode, pl->lds_cap, s);
-        void* dst[4] = {o->ax, o->ay, o->az, o->dudt};
-        for (int k = 0; k < 4; ++k) launch_unsort<double>(n, b.rank, (double*)b.f_out + k * n, dst[k], s);
-    } else {
-        launch_prep_dens<float>(b, sc, d, s);
-        launch_hmax_pyramid<float>(b, sc, s);
-        r = launch_force<float>(b, sc, mode, pl->lds_cap, s);
-        void* dst[4] = {o->ax, o->ay, o->az, o->dudt};
-        for (int k = 0; k < 4; ++k) launch_unsort<float>(n, b.rank, (float*)b.f_out + k * n, dst[k], s);
-    }
-    if (o->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, o->nint, s);
-    if (r) return fail(SWSPH_E_HIP, "force kernel launch failed");
-    return hip_check(hipGetLastError(), "force");
+    if (pl && !o) return fail(SWSPH_E_ARG, "force output is NULL");
+    return gf_checked(pl, p, d, nullptr, o, ws, stream);
 }
 
 int swsph_kernel_times(swsph_plan* pl, double ms[4], uint64_t launches[4], void* stream) {
@@ -640,10 +639,6 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
 
 }  // extern "C"
 
-extern "C" {
-
-}  // extern "C"
-
 namespace {
 
 // Everything a captured step depends on: pointers, sizes, box data and the
@@ -693,14 +688,7 @@ int step_eager(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
     if (r) return r;
     r = swsph_density(pl, p, d, ws, stream);
     if (r) return r;
-    if (go) {
-        r = swsph_gradient(pl, p, d, go, ws, stream);
-        if (r) return r;
-    }
-    if (fo) {
-        r = swsph_force(pl, p, d, fo, ws, stream);
-        if (r) return r;
-    }
+    if (go || fo) return gf_checked(pl, p, d, go, fo, ws, stream);
     return SWSPH_OK;
 }
 
@@ -740,8 +728,7 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
         if (r) return r;
         bin_enqueue(pl, p, pl->cap);
         int rr = swsph_density(pl, p, d, ws, pl->cap);
-        if (!rr && go) rr = swsph_gradient(pl, p, d, go, ws, pl->cap);
-        if (!rr && fo) rr = swsph_force(pl, p, d, fo, ws, pl->cap);
+        if (!rr && (go || fo)) rr = gf_checked(pl, p, d, go, fo, ws, pl->cap);
         hipGraph_t g = nullptr;
         r = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
         if (!r && rr) r = rr;

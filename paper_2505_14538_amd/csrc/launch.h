@@ -97,13 +97,13 @@ void launch_prep_dens(const BinPtrs& b, const Scheme& sc, const swsph_density_ou
                       hipStream_t s);
 template <typename T>
 void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s);
+// The task lists both loops below read (build before either).
+template <typename T>
+void launch_gf_tasks(const BinPtrs& b, const Scheme& sc, hipStream_t s);
 template <typename T>
 int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
 template <typename T>
 int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
-template <typename T>
-int launch_step_fused(const BinPtrs& b, const Scheme& sc, int lds_cap, bool do_grad,
-                      bool do_force, hipStream_t s);
 template <typename T>
 int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* g,
                     const swsph_density_out* d, int lds_cap, hipStream_t s);

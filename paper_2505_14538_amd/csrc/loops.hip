@@ -119,10 +119,13 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
             if (fabs(G - Tt) <= a.h_tol * Tt) {
                 conv = true;
             } else {
-                const T dG = ((T)3 * S0r - S1r) / h;
+                // Newton step on log G over log h (h dG/dh = 3 S0 - S1): the
+                // same root, reached in fewer sweeps than a step on G itself,
+                // since G grows about as h^3
+                const T dl = (T)3 * S0r - S1r;
                 if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
-                T hn = h - (G - Tt) / dG;
-                const bool ok = dG > (T)0 && hn > lo_h && hn < hi_h;
+                T hn = h * exp(-log1p((G - Tt) / Tt) * G / dl);
+                const bool ok = dl > (T)0 && hn > lo_h && hn < hi_h;
                 if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
                 if (!has_upper && hn >= hedge) {
                     // the step leaves the staged set: first try its edge; if
@@ -249,7 +252,12 @@ __device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t, W
     const T H = mul_unfused(eps, h);
     const T H2 = act ? mul_unfused(H, H) : (T)-1;
     const T invH = (T)1 / H;
-    const T R = (T)a.trad[t];
+    // the tile's own radius, formed as a gradient-only task build forms it
+    // (the list comes from the force build, whose radius is never smaller)
+    const T hmax = wave_max(act ? h : (T)0);
+    const T Rg = (T)(float)(eps * hmax * (T)(1 + 4e-7));
+    const T Rt = (T)a.trad[t];
+    const T R = Rg < Rt ? Rg : Rt;
     const T ci = di.z, ui = vi.w;
     T vsig = (T)2 * ci, lap = 0;
     unsigned long long tested = 0;
@@ -493,11 +501,19 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     }
     return r;
 }
+// Task lists of the gradient and force loops: one build serves both.  The
+// force list (support max(H_i, H_j)) contains every pair the gradient loop
+// needs (support H_i); the gradient loop culls it to its own radius while
+// staging, which leaves exactly the set a gradient-only search would list.
+template <typename T>
+void launch_gf_tasks(const BinPtrs& b, const Scheme& sc, hipStream_t s) {
+    launch_hmax_pyramid<T>(b, sc, s);
+    launch_tasks<T>(b, sc, 2, false, s);
+}
 template <typename T>
 int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.g_out;
-    launch_tasks<T>(b, sc, 1, false, s);
     timer_begin(sc.timer, 1, s);
     const int r = launch_loop<L_GRAD, T>(a, mode, lds_cap, 1, s);
     timer_end(sc.timer, 1, s);
@@ -508,7 +524,6 @@ int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipS
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.f_out;
     a.iout = b.f_int;
-    launch_tasks<T>(b, sc, 2, false, s);
     timer_begin(sc.timer, 2, s);
     const int r = launch_loop<L_FORCE, T>(a, mode, lds_cap, 2, s);
     timer_end(sc.timer, 2, s);
@@ -517,6 +532,8 @@ int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipS
 
 template int launch_density<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_density<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template void launch_gf_tasks<float>(const BinPtrs&, const Scheme&, hipStream_t);
+template void launch_gf_tasks<double>(const BinPtrs&, const Scheme&, hipStream_t);
 template int launch_gradient<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_gradient<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_force<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);

@@ -34,6 +34,7 @@ struct TArgs {
     int32_t leaf_max;
     const V4<T>* pos4;
     int64_t n;
+    const int32_t* list;  // tiles to build (first *ntiles entries), or null: every tile
 };
 
 // Task list of tile t: its candidate j-particles -- the particles of the
@@ -57,8 +58,54 @@ struct TaskMem {
     uint32_t buf[TASK_BUF];
 };
 
+// The particles of a batch of leaves (cell ranges with image codes, their
+// counts' prefix sums in lpre), visited in order, WAVE x U at a time: the
+// particle index of every slot is found first and all their loads are issued
+// together, so a wavefront waits for one memory round trip per U x 64
+// candidates instead of one per 64.  visit(have, j, code, pos, h_j) is called
+// by the whole wavefront (it may ballot); lanes past the end get have=false.
+constexpr int CAND_U = 4;
+
+template <typename T, bool NEEDH, typename F>
+__device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_t* lpre, int nl,
+                                               int nv, const V4<T>* __restrict__ pos4,
+                                               const T* __restrict__ hs, int64_t n, F&& visit) {
+    const int lane = lane_id();
+    for (int v0 = 0; v0 < nv; v0 += CAND_U * WAVE) {
+        int jj[CAND_U], cc[CAND_U];
+#pragma unroll
+        for (int u = 0; u < CAND_U; ++u) {
+            const int v = v0 + u * WAVE + lane;
+            jj[u] = 0;
+            cc[u] = 0;
+            if (v < nv) {
+                int lo = 0, hi = nl - 1;
+                while (lo < hi) {  // last leaf whose prefix is <= v
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                const int j = sm.lbeg[lo] + (v - lpre[lo]);
+                jj[u] = (j < 0 || j >= (int)n) ? 0 : j;  // cannot happen with a valid cell table
+                cc[u] = sm.lshift[lo];
+            }
+        }
+        V4<T> pa[CAND_U];
+        T hj[CAND_U];
+#pragma unroll
+        for (int u = 0; u < CAND_U; ++u) pa[u] = pos4[jj[u]];
+#pragma unroll
+        for (int u = 0; u < CAND_U; ++u) hj[u] = NEEDH ? hs[jj[u]] : (T)0;
+#pragma unroll
+        for (int u = 0; u < CAND_U; ++u) {
+            if (v0 + u * WAVE >= nv) break;  // uniform
+            visit(v0 + u * WAVE + lane < nv, jj[u], cc[u], pa[u], hj[u]);
+        }
+    }
+}
+
+// Returns the number of entries listed for the tile (uniform over the wave).
 template <typename T, int MODE>
-__device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t, int fixup) {
+__device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t, int fixup) {
     const int lane = lane_id();
     const BoxInfo bi = a.boxtab[tl.box];
     const float L = (float)bi.L;
@@ -90,7 +137,7 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
     const T R2t = Rt * Rt;  // the loops cull with the same value
     const T Lt = (T)bi.L;
     bool direct = false;    // second round: write to global memory at base
-    int64_t base = 0, known = 0;
+    int64_t base = 0, known = 0, listed = 0;
     for (int round = 0; round < 2; ++round) {
         SearchState st;
         search_init(m.sm, st, bi, g, Rstart);
@@ -111,46 +158,39 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
                 wave_sync();
                 const int nl = st.nleaf;
                 const int nv = tot0 + tot1;
-                for (int v0 = 0; v0 < nv; v0 += WAVE) {
-                    const int v = v0 + lane;
-                    bool pass = false;
-                    uint32_t ent = 0;
-                    if (v < nv) {
-                        int lo = 0, hi = nl - 1;
-                        while (lo < hi) {  // last leaf whose prefix is <= v
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
+                for_candidates<T, MODE == 2>(
+                    m.sm, m.lpre, nl, nv, a.pos4, a.hs, a.n,
+                    [&](bool have, int j, int code, const V4<T>& pa, T hj) {
+                        bool pass = false;
+                        uint32_t ent = 0;
+                        if (have) {
+                            int sx, sy, sz;
+                            shift_of(code, sx, sy, sz);
+                            const T xs = pa.x + (T)sx * Lt, ys = pa.y + (T)sy * Lt,
+                                    zs = pa.z + (T)sz * Lt;
+                            const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
+                            const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
+                            const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
+                            const T d2 = dist2_unfused(gx, gy, gz);
+                            T crit = R2t;
+                            if (MODE == 2) {
+                                const T Hj = mul_unfused(a.eps, hj);
+                                crit = max(crit, mul_unfused(Hj, Hj));
+                            }
+                            pass = d2 < crit;
+                            ent = (uint32_t)j | ((uint32_t)code << 26);
                         }
-                        int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
-                        if (j < 0 || j >= (int)a.n) j = 0;  // cannot happen with a valid cell table
-                        const int code = m.sm.lshift[lo];
-                        int sx, sy, sz;
-                        shift_of(code, sx, sy, sz);
-                        const V4<T> pa = a.pos4[j];
-                        const T xs = pa.x + (T)sx * Lt, ys = pa.y + (T)sy * Lt, zs = pa.z + (T)sz * Lt;
-                        const T gx = max((T)0, max((T)g.lo[0] - xs, xs - (T)g.hi[0]));
-                        const T gy = max((T)0, max((T)g.lo[1] - ys, ys - (T)g.hi[1]));
-                        const T gz = max((T)0, max((T)g.lo[2] - zs, zs - (T)g.hi[2]));
-                        const T d2 = dist2_unfused(gx, gy, gz);
-                        T crit = R2t;
-                        if (MODE == 2) {
-                            const T Hj = mul_unfused(a.eps, a.hs[j]);
-                            crit = max(crit, mul_unfused(Hj, Hj));
+                        const unsigned long long pm = ballot(pass);
+                        if (pass) {
+                            const int64_t at = total + mbcnt(pm);
+                            if (direct) {
+                                if (at < known) a.cands[base + at] = ent;
+                            } else if (at < TASK_BUF) {
+                                m.buf[at] = ent;
+                            }
                         }
-                        pass = d2 < crit;
-                        ent = (uint32_t)j | ((uint32_t)code << 26);
-                    }
-                    const unsigned long long pm = ballot(pass);
-                    if (pass) {
-                        const int64_t at = total + mbcnt(pm);
-                        if (direct) {
-                            if (at < known) a.cands[base + at] = ent;
-                        } else if (at < TASK_BUF) {
-                            m.buf[at] = ent;
-                        }
-                    }
-                    total += __popcll(pm);
-                }
+                        total += __popcll(pm);
+                    });
                 st.nleaf = 0;
                 wave_sync();
             }
@@ -159,9 +199,9 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
         if (direct) break;
         // first round: record, allocate, copy (or go round again)
         int64_t at = 0;
+        listed = total;
         if (lane == 0) {
             a.tiles[t].cost = (float)tl.count * (float)total;
-            atomicAdd(&a.cnt->listed, (unsigned long long)total);
             at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
             const bool fits = at + total <= a.cand_cap;
             a.cand_off[t] = fits ? (int32_t)at : -1;
@@ -183,6 +223,7 @@ __device__ void task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t 
         wave_sync();
     }
     wave_sync();
+    return listed;
 }
 
 // MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
@@ -196,7 +237,9 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
     const int lane = lane_id();
     const int64_t nt = (int64_t)*a.ntiles;
     const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
-    for (int64_t t = blockIdx.x * (int64_t)TASK_WPB + wave; t < nt; t += nw) {
+    unsigned long long listed = 0;  // flushed once per wavefront
+    for (int64_t k = blockIdx.x * (int64_t)TASK_WPB + wave; k < nt; k += nw) {
+        const int64_t t = a.list ? (int64_t)uniform(a.list[k]) : k;
         Tile tl = a.tiles[t];
         tl.count = uniform(tl.count);
         tl.box = uniform(tl.box);
@@ -208,8 +251,9 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
             }
             continue;
         }
-        task_one<T, MODE>(a, m, tl, t, fixup);
+        listed += (unsigned long long)task_one<T, MODE>(a, m, tl, t, fixup);
     }
+    if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
 }
 
 // Queue order of the tiles by decreasing cost (longest task first), so the
@@ -320,6 +364,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
     const int lane = lane_id();
     const int64_t np = (int64_t)*a.ntiles;
     const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
+    unsigned long long listed = 0;  // flushed once per wavefront
     for (int64_t p = blockIdx.x * (int64_t)TASK_WPB + wave; p < np; p += nw) {
         const Tile tp = a.tiles[p];
         const int d0 = uniform(dfirst[p]);
@@ -388,23 +433,14 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                     wave_sync();
                     const int nl = st.nleaf;
                     const int nv = tot0 + tot1;
-                    for (int v0 = 0; v0 < nv; v0 += WAVE) {
-                        const int v = v0 + lane;
+                    for_candidates<T, false>(
+                        m.sm, m.lpre, nl, nv, a.pos4, a.hs, a.n,
+                        [&](bool have, int j, int code, const V4<T>& pa, T) {
                         T xs = 0, ys = 0, zs = 0;
                         uint32_t ent = 0;
-                        const bool have = v < nv;
                         if (have) {
-                            int lo = 0, hi = nl - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (m.lpre[mid] <= v) lo = mid; else hi = mid - 1;
-                            }
-                            int j = m.sm.lbeg[lo] + (v - m.lpre[lo]);
-                            if (j < 0 || j >= (int)a.n) j = 0;
-                            const int code = m.sm.lshift[lo];
                             int sx, sy, sz;
                             shift_of(code, sx, sy, sz);
-                            const V4<T> pa = a.pos4[j];
                             xs = pa.x + (T)sx * Lt;
                             ys = pa.y + (T)sy * Lt;
                             zs = pa.z + (T)sz * Lt;
@@ -424,7 +460,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                             }
                             if (lane == c) run += __popcll(pm);
                         }
-                    }
+                    });
                     st.nleaf = 0;
                     wave_sync();
                 }
@@ -435,10 +471,8 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                 int tot = 0;
                 const int e = wave_excl_scan(lane < nd ? run : 0, tot);
                 int64_t base = 0;
-                if (lane == 0) {
-                    base = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)tot);
-                    atomicAdd(&a.cnt->listed, (unsigned long long)tot);
-                }
+                if (lane == 0) base = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)tot);
+                listed += (unsigned long long)tot;
                 base = __shfl(base, 0, WAVE);
                 const bool fits = base + tot <= a.cand_cap;
                 if (!fits && lane == 0) latch(a.cnt, SWSPH_ST_CAPACITY);
@@ -454,6 +488,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
         }
         wave_sync();
     }
+    if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
 }
 
 template <typename T>
@@ -493,6 +528,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.leaf_max = sc.leaf_max;
     a.pos4 = (const V4<T>*)b.pos4;
     a.n = b.n;
+    a.list = nullptr;
     return a;
 }
 
@@ -501,6 +537,11 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     if (b.n <= 0) return;
     const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? 1.25 : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
+    if (fixup) {
+        // the flagged density tiles, compacted by k_fix_list
+        a.list = b.tmpidx;
+        a.ntiles = &b.cnt->n_fix;
+    }
     const dim3 block(TASK_WPB * WAVE);
     void (*kern)(TArgs<T>, int) =
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
