@@ -116,7 +116,6 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     const uint64_t N = (uint64_t)n, T = (uint64_t)tsz;
     l.counters = take(sizeof(Counters));
     l.boxtab = take(sizeof(BoxInfo) * n_box);
-    l.phase = take(sizeof(uint32_t) * 4 * n_box);
     l.keys = take(4 * N);
     l.slot = take(4 * N);
     l.tmpidx = take(4 * (N + 1));
@@ -278,7 +277,6 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     BinPtrs b;
     b.cnt = (Counters*)(w + l.counters);
     b.boxtab = (BoxInfo*)(w + l.boxtab);
-    b.phase = (uint32_t*)(w + l.phase);
     b.keys = (uint32_t*)(w + l.keys);
     b.slot = (int32_t*)(w + l.slot);
     b.tmpidx = (int32_t*)(w + l.tmpidx);

@@ -25,7 +25,6 @@ struct Scheme {
 struct BinPtrs {
     Counters* cnt;
     BoxInfo* boxtab;
-    uint32_t* phase;
     uint32_t* keys;
     int32_t *slot, *tmpidx, *perm, *rank;
     int32_t *fine_count, *cstart, *scan_part;

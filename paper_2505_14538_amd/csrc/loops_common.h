@@ -365,39 +365,64 @@ struct WaveStats {
 constexpr int QCHUNK = 2;
 constexpr int NXCD = 8;
 
-template <class Run>
-__device__ __forceinline__ void pop_segment(unsigned long long* head, int64_t b, int64_t e,
-                                            int64_t cap, const int32_t* order, Run&& run) {
-    for (int64_t guard = 0; guard <= cap; ++guard) {
-        int t0 = 0;
-        if (lane_id() == 0) t0 = (int)atomicAdd(head, (unsigned long long)QCHUNK);
-        const int64_t s0 = b + uniform(__shfl(t0, 0, WAVE));
-        if (s0 >= e) break;
-        const int64_t s1 = min(s0 + QCHUNK, e);
-        for (int64_t t = s0; t < s1; ++t) run(order[t]);
-    }
-}
-
+// One call site of `run` (the tile body is inlined once): the loop keeps a
+// range [next, end) of queue positions in hand and refills it from the
+// dispatch of the mode.  Bounded: each queue segment takes at most
+// tile_cap + 1 pops, flat and per-task ranges advance every refill.
 template <typename T, class Run>
 __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&& run) {
     const int wave = threadIdx.x / WAVE;
     const int64_t nt = (int64_t)*a.ntask;
-    if (mode == MODE_QUEUE) {
-        if (a.xcd_split) {
-            const int x0 = xcc_id() % NXCD;
-            for (int y = 0; y < NXCD; ++y) {
+    const bool queue = mode == MODE_QUEUE;
+    const bool split = queue && a.xcd_split;
+    const int nseg = split ? NXCD : 1;
+    const int x0 = split ? xcc_id() % NXCD : 0;
+    int y = 0;         // queue: segments left behind
+    int64_t pops = 0;  // queue: pops on the current segment
+    bool pre = false;  // queue: a pop of the current segment is in flight
+    int pv = 0;
+    int64_t next = 0, end = 0;
+    int64_t flat = blockIdx.x * (int64_t)WPB + wave;
+    const int64_t fstep = (int64_t)gridDim.x * WPB;
+    bool once = wave == 0;
+    const int64_t guard_max = 2 * nt + (int64_t)nseg * (a.tile_cap + 2) + 2;
+    for (int64_t guard = 0; guard < guard_max; ++guard) {
+        if (next >= end) {
+            if (queue) {
+                if (y >= nseg) break;
                 const int x = (x0 + y) % NXCD;
-                pop_segment(&a.queue[x], nt * x / NXCD, nt * (x + 1) / NXCD, a.tile_cap, a.order,
-                            run);
+                const int64_t b = split ? nt * x / NXCD : 0;
+                const int64_t e = split ? nt * (x + 1) / NXCD : nt;
+                unsigned long long* head = &a.queue[split ? x : 0];
+                int t0 = pv;
+                if (!pre && lane_id() == 0) t0 = (int)atomicAdd(head, (unsigned long long)QCHUNK);
+                pre = false;
+                const int64_t s0 = b + uniform(t0);
+                if (s0 >= e || ++pops > a.tile_cap + 1) {
+                    ++y;
+                    pops = 0;
+                    continue;
+                }
+                next = s0;
+                end = min(s0 + QCHUNK, e);
+                // the next pop goes out now; its latency hides behind these tasks
+                if (lane_id() == 0) pv = (int)atomicAdd(head, (unsigned long long)QCHUNK);
+                pre = true;
+            } else if (mode == MODE_FLAT) {
+                if (flat >= nt) break;
+                next = flat;
+                end = flat + 1;
+                flat += fstep;
+            } else {
+                if (!once || a.task < 0 || a.task >= nt) break;
+                once = false;
+                next = a.task;
+                end = next + 1;
             }
-        } else {
-            pop_segment(&a.queue[0], 0, nt, a.tile_cap, a.order, run);
         }
-    } else if (mode == MODE_FLAT) {
-        const int64_t nw = (int64_t)gridDim.x * WPB;
-        for (int64_t t = blockIdx.x * (int64_t)WPB + wave; t < nt; t += nw) run(a.order[t]);
-    } else {
-        if (wave == 0 && a.task >= 0 && a.task < nt) run(a.task);
+        // per-task: the launch names the tile itself; otherwise a queue position
+        run(mode == MODE_PER_TASK ? (int)next : (int)a.order[next]);
+        ++next;
     }
 }
 

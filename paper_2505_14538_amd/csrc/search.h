@@ -198,16 +198,26 @@ __device__ inline bool search_step(SearchMem& m, SearchState& st, const BoxInfo&
     return st.head >= st.tail;
 }
 
-// Exclusive prefix sum across the wavefront (total in `total`).
+// Exclusive prefix sum across the wavefront (total in `total`); every lane
+// must be active.  Inclusive sums within each row of 16 lanes by DPP row
+// shifts (source lanes before the row start read 0), then the row totals
+// from lanes 15, 31, 47 and 63 by register reads: no LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ int row_shr_add(int x) {
+    return x + __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
+}
 __device__ __forceinline__ int wave_excl_scan(int v, int& total) {
     const int lane = lane_id();
     int x = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int t = __shfl_up(x, o, WAVE);
-        if (lane >= o) x += t;
-    }
-    total = __shfl(x, WAVE - 1, WAVE);
+    x = row_shr_add<0x111>(x);  // row_shr:1
+    x = row_shr_add<0x112>(x);  // row_shr:2
+    x = row_shr_add<0x114>(x);  // row_shr:4
+    x = row_shr_add<0x118>(x);  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31);
+    const int r2 = __builtin_amdgcn_readlane(x, 47), r3 = __builtin_amdgcn_readlane(x, 63);
+    const int row = lane >> 4;
+    x += (row > 0 ? r0 : 0) + (row > 1 ? r1 : 0) + (row > 2 ? r2 : 0);
+    total = r0 + r1 + r2 + r3;
     return x - v;
 }
 

@@ -55,7 +55,7 @@ struct Counters {
     unsigned long long listed;
     unsigned long long restages;
     unsigned long long queue[4][8];    // task-queue heads per loop (8: one per XCD segment)
-    unsigned long long leaf_need;      // leaves requested by the last task build
+    unsigned long long build_queue[8]; // item-queue heads of the task builds
     unsigned long long n_tiles;        // tiles of the gradient/force (and adjoint) loops
     unsigned long long n_tiles_d;      // tiles of the density loop
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
@@ -67,7 +67,7 @@ enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD =
 
 // Byte offsets of every workspace region (computed on the host).
 struct Layout {
-    uint64_t counters, boxtab, phase;      // phase: per-box done counters (2 per box)
+    uint64_t counters, boxtab;
     uint64_t keys, slot, tmpidx, perm, rank;  // slot/tmpidx: reused for the tile scan
     uint64_t fine_count, cstart, scan_part;
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
@@ -116,6 +116,57 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // register (read only).
 __device__ __forceinline__ int xcc_id() {
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15;  // hwreg(XCC_ID, 0, 4)
+}
+
+// Items [0, n) handed to wavefronts on demand, so a few costly items do not
+// hold up a static schedule.  With `split` the range is cut into NSEG
+// segments (one per XCD; heads[NSEG] start at zero) and a wavefront pops
+// from its own XCD's segment first (hardware XCC id), then helps the others;
+// otherwise heads[0] serves the whole range.  One item per pop, the next pop
+// issued before the current item runs (its latency hides behind the work).
+// f(k) is called by the whole wavefront at one site.  Bounded: every
+// iteration takes one item or moves to the next segment.
+constexpr int NSEG = 8;
+template <class F>
+__device__ __forceinline__ void for_each_item(unsigned long long* heads, int64_t n, bool split,
+                                              F&& f) {
+    const int nseg = split ? NSEG : 1;
+    const int x0 = split ? xcc_id() % NSEG : 0;
+    int y = 0, x = x0;
+    int64_t b = split ? n * x / NSEG : 0, e = split ? n * (x + 1) / NSEG : n;
+    int v = 0;
+    if (lane_id() == 0) v = (int)atomicAdd(&heads[x], 1ull);
+    int64_t k = b + (int64_t)uniform(v);
+    const int64_t guard_max = n + 2 * NSEG + 2;
+    for (int64_t guard = 0; guard < guard_max; ++guard) {
+        if (k >= e) {
+            if (++y >= nseg) break;
+            x = (x0 + y) % NSEG;
+            b = n * x / NSEG;
+            e = n * (x + 1) / NSEG;
+            int w = 0;
+            if (lane_id() == 0) w = (int)atomicAdd(&heads[x], 1ull);
+            k = b + (int64_t)uniform(w);
+            continue;
+        }
+        int vn = 0;
+        if (lane_id() == 0) vn = (int)atomicAdd(&heads[x], 1ull);
+        f(k);
+        k = b + (int64_t)uniform(vn);
+    }
+}
+
+// The value lane c holds (c the same in every lane): a register read across
+// lanes, no LDS round trip.
+__device__ __forceinline__ int lane_val(int v, int c) { return __builtin_amdgcn_readlane(v, c); }
+__device__ __forceinline__ float lane_val(float v, int c) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), c));
+}
+__device__ __forceinline__ double lane_val(double v, int c) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, c);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), c);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 __device__ __forceinline__ float shfl_xor(float v, int m) { return __shfl_xor(v, m, WAVE); }

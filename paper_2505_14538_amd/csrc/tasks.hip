@@ -35,6 +35,7 @@ struct TArgs {
     const V4<T>* pos4;
     int64_t n;
     const int32_t* list;  // tiles to build (first *ntiles entries), or null: every tile
+    unsigned long long* heads;  // item-queue heads (NSEG, zeroed before the launch)
 };
 
 // Task list of tile t: its candidate j-particles -- the particles of the
@@ -71,7 +72,22 @@ __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_
                                                int nv, const V4<T>* __restrict__ pos4,
                                                const T* __restrict__ hs, int64_t n, F&& visit) {
     const int lane = lane_id();
+    int top = 1;  // largest power of two <= nl (uniform)
+    while (2 * top <= nl) top *= 2;
     for (int v0 = 0; v0 < nv; v0 += CAND_U * WAVE) {
+        // leaf of slot v: the last leaf whose prefix is <= v (prefixes rise
+        // strictly, lpre[0] = 0), by binary lifting with a uniform step count
+        // so the slots' LDS reads overlap
+        int lo[CAND_U];
+#pragma unroll
+        for (int u = 0; u < CAND_U; ++u) lo[u] = 0;
+        for (int st = top; st > 0; st >>= 1) {
+#pragma unroll
+            for (int u = 0; u < CAND_U; ++u) {
+                const int c = lo[u] + st;
+                if (c < nl && lpre[c] <= v0 + u * WAVE + lane) lo[u] = c;
+            }
+        }
         int jj[CAND_U], cc[CAND_U];
 #pragma unroll
         for (int u = 0; u < CAND_U; ++u) {
@@ -79,14 +95,9 @@ __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_
             jj[u] = 0;
             cc[u] = 0;
             if (v < nv) {
-                int lo = 0, hi = nl - 1;
-                while (lo < hi) {  // last leaf whose prefix is <= v
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (lpre[mid] <= v) lo = mid; else hi = mid - 1;
-                }
-                const int j = sm.lbeg[lo] + (v - lpre[lo]);
+                const int j = sm.lbeg[lo[u]] + (v - lpre[lo[u]]);
                 jj[u] = (j < 0 || j >= (int)n) ? 0 : j;  // cannot happen with a valid cell table
-                cc[u] = sm.lshift[lo];
+                cc[u] = sm.lshift[lo[u]];
             }
         }
         V4<T> pa[CAND_U];
@@ -228,7 +239,7 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64
 
 // MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
 // 2 force (eps*hmax, and cells whose own support reaches the tile).
-// One wavefront per tile, grid-stride over the device tile count.
+// One wavefront per tile; tiles are popped from the item queue (for_each_item).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup) {
     __shared__ TaskMem smem_task[TASK_WPB];
@@ -236,9 +247,8 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
     TaskMem& m = smem_task[wave];
     const int lane = lane_id();
     const int64_t nt = (int64_t)*a.ntiles;
-    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
     unsigned long long listed = 0;  // flushed once per wavefront
-    for (int64_t k = blockIdx.x * (int64_t)TASK_WPB + wave; k < nt; k += nw) {
+    for_each_item(a.heads, nt, a.list == nullptr, [&](int64_t k) {
         const int64_t t = a.list ? (int64_t)uniform(a.list[k]) : k;
         Tile tl = a.tiles[t];
         tl.count = uniform(tl.count);
@@ -249,10 +259,10 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
                 a.cand_cnt[t] = 0;
                 if (!fixup) a.trad[t] = 0.f;
             }
-            continue;
+            return;
         }
         listed += (unsigned long long)task_one<T, MODE>(a, m, tl, t, fixup);
-    }
+    });
     if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
 }
 
@@ -350,9 +360,6 @@ void launch_order(const BinPtrs& b, hipStream_t s) {
 struct GroupMem {
     SearchMem sm;
     int32_t lpre[LEAFCAP + 1];
-    float lo[WAVE][3], hi[WAVE][3];  // member boxes
-    float R[WAVE];                   // member radii
-    int32_t off[WAVE];               // member list offsets
 };
 
 template <typename T>
@@ -363,24 +370,28 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
     GroupMem& m = smem_group[wave];
     const int lane = lane_id();
     const int64_t np = (int64_t)*a.ntiles;
-    const int64_t nw = (int64_t)gridDim.x * TASK_WPB;
     unsigned long long listed = 0;  // flushed once per wavefront
-    for (int64_t p = blockIdx.x * (int64_t)TASK_WPB + wave; p < np; p += nw) {
+    for_each_item(a.heads, np, true, [&](int64_t p) {
         const Tile tp = a.tiles[p];
         const int d0 = uniform(dfirst[p]);
         int nd = uniform(dfirst[p + 1]) - d0;
         if (nd > WAVE) nd = WAVE;  // a group has at most 64 particles
-        if (nd <= 0) continue;
+        if (nd <= 0) return;
         const BoxInfo bi = a.boxtab[uniform(tp.box)];
         const float L = (float)bi.L;
         const float Rcap = 0.5f * L * (1.0f - 1e-6f);
-        // members: boxes, radii (from the largest h guess of each)
+        // members: lane c < nd holds member c's box, radius and list offset
+        // (read by the other lanes with lane_val); radii from the largest h
+        // guess of each member
         Tile tm;
+        float blo[3] = {0.f, 0.f, 0.f}, bhi[3] = {0.f, 0.f, 0.f};
         if (lane < nd) {
             tm = tiles_d[d0 + lane];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) { m.lo[lane][d] = tm.lo[d]; m.hi[lane][d] = tm.hi[d]; }
+            for (int d = 0; d < 3; ++d) { blo[d] = tm.lo[d]; bhi[d] = tm.hi[d]; }
         }
+        float Rl = 0.f;
+        int moff = 0;
         const int pc = uniform(tp.count);
         const int pb = uniform(tp.begin);
         const T h = lane < pc ? a.hs[pb + lane] : (T)0;
@@ -396,17 +407,14 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                 R = Rcap;
             }
             if (!(R > 0.f)) R = Rcap;
-            if (lane == 0) {
-                m.R[c] = R;
-                a.trad[d0 + c] = R;
-            }
+            if (lane == 0) a.trad[d0 + c] = R;
+            if (lane == c) Rl = R;
             Rmax = fmaxf(Rmax, R);
         }
-        wave_sync();
         // member c's squared radius, in lane c, formed as the loops form it
         T R2c = (T)0;
         if (lane < nd) {
-            const T Rt = (T)m.R[lane];
+            const T Rt = (T)Rl;
             R2c = Rt * Rt;
         }
         TileGeom g;
@@ -447,15 +455,19 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                             ent = (uint32_t)j | ((uint32_t)code << 26);
                         }
                         for (int c = 0; c < nd; ++c) {
-                            const T r2c = __shfl(R2c, c, WAVE);
-                            const T gx = max((T)0, max((T)m.lo[c][0] - xs, xs - (T)m.hi[c][0]));
-                            const T gy = max((T)0, max((T)m.lo[c][1] - ys, ys - (T)m.hi[c][1]));
-                            const T gz = max((T)0, max((T)m.lo[c][2] - zs, zs - (T)m.hi[c][2]));
+                            const T r2c = lane_val(R2c, c);
+                            const T lx = (T)lane_val(blo[0], c), hx = (T)lane_val(bhi[0], c);
+                            const T ly = (T)lane_val(blo[1], c), hy = (T)lane_val(bhi[1], c);
+                            const T lz = (T)lane_val(blo[2], c), hz = (T)lane_val(bhi[2], c);
+                            const T gx = max((T)0, max(lx - xs, xs - hx));
+                            const T gy = max((T)0, max(ly - ys, ys - hy));
+                            const T gz = max((T)0, max(lz - zs, zs - hz));
                             const bool pass_c = have && dist2_unfused(gx, gy, gz) < r2c;
                             const unsigned long long pm = ballot(pass_c);
-                            const int run_c = __shfl(run, c, WAVE);
+                            const int run_c = lane_val(run, c);
+                            const int off_c = lane_val(moff, c);
                             if (pass == 1 && pass_c) {
-                                const int64_t at = (int64_t)m.off[c] + run_c + mbcnt(pm);
+                                const int64_t at = (int64_t)off_c + run_c + mbcnt(pm);
                                 if (at < a.cand_cap) a.cands[at] = ent;
                             }
                             if (lane == c) run += __popcll(pm);
@@ -477,7 +489,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                 const bool fits = base + tot <= a.cand_cap;
                 if (!fits && lane == 0) latch(a.cnt, SWSPH_ST_CAPACITY);
                 if (lane < nd) {
-                    m.off[lane] = (int32_t)(base + e);
+                    moff = (int32_t)(base + e);
                     a.cand_off[d0 + lane] = fits ? (int32_t)(base + e) : -1;
                     a.cand_cnt[d0 + lane] = fits ? run : 0;
                     tiles_d[d0 + lane].cost = (float)tm.count * (float)run;
@@ -487,12 +499,33 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
             }
         }
         wave_sync();
-    }
+    });
     if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
 }
 
 template <typename T>
 static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin);
+
+// Resident workgroups of a build kernel (items are popped, so a larger grid
+// only adds empty pops).
+static unsigned resident_grid(const void* kern, int threads) {
+    static const void* keys[16];
+    static unsigned vals[16];
+    for (int i = 0; i < 16; ++i)
+        if (keys[i] == kern) return vals[i];
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const unsigned g = (unsigned)(per_cu * device_cu_count());
+    for (int i = 0; i < 16; ++i)
+        if (!keys[i]) {
+            keys[i] = kern;
+            vals[i] = g;
+            break;
+        }
+    return g;
+}
 
 // The first density task build with grouped searches (density tiles smaller
 // than the gradient/force tiles).
@@ -502,7 +535,9 @@ void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s) {
     const double margin = (sc.flags & SWSPH_FIXED_H) ? 1.0 : 1.25;
     TArgs<T> a = targs<T>(bin, sc, margin);
     launch_fill_u32(&bin.cnt->cand_used, 2, 0u, s);
-    hipLaunchKernelGGL(k_tasks_group<T>, dim3(wave_grid(bin.tile_cap, TASK_WPB)),
+    launch_fill_u32(a.heads, 2 * NSEG, 0u, s);
+    hipLaunchKernelGGL(k_tasks_group<T>,
+                       dim3(resident_grid((const void*)k_tasks_group<T>, TASK_WPB * WAVE)),
                        dim3(TASK_WPB * WAVE), 0, s, a, bin.tiles_d, (const int32_t*)bin.dfirst);
 }
 
@@ -529,6 +564,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.pos4 = (const V4<T>*)b.pos4;
     a.n = b.n;
     a.list = nullptr;
+    a.heads = b.cnt->build_queue;
     return a;
 }
 
@@ -546,7 +582,9 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     void (*kern)(TArgs<T>, int) =
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
     launch_fill_u32(&b.cnt->cand_used, 2, 0u, s);
-    hipLaunchKernelGGL(kern, dim3(wave_grid(b.tile_cap, TASK_WPB)), block, 0, s, a, (int)fixup);
+    launch_fill_u32(a.heads, 2 * NSEG, 0u, s);
+    hipLaunchKernelGGL(kern, dim3(resident_grid((const void*)kern, TASK_WPB * WAVE)), block, 0, s, a,
+                       (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
 template void launch_tasks_grouped<float>(const BinPtrs&, const Scheme&, hipStream_t);
