@@ -65,13 +65,13 @@ def cpu_baseline(parts):
                       "(%.1f s) + force on %d random particles (%.1f s)" % (parts.n, t_d, ns, t_f)}
 
 
-def per_task_step(S, dp, n_tiles):
+def per_task_step(S, dp, n_tiles, tuning):
     """One step with one kernel launch per tile task (the same tile bodies):
     the per-task offload baseline."""
     import torch
     log("per-task launch step (%d tasks per loop)" % n_tiles)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pt = S.Plan(flags=S.PER_TASK_LAUNCH)
+    pt = S.Plan(flags=S.PER_TASK_LAUNCH, **tuning)
     torch.cuda.synchronize()
     ev0.record()
     pt.bin(dp)
@@ -113,8 +113,14 @@ def run(args):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # the batched path: the whole step captured in a HIP graph by the library
-    # (bin + three persistent loop launches), replayed each step
+    # (bin + three persistent loop launches), replayed each step; the plan's
+    # options (tile sizes, LDS capacities, task order) from the library's
+    # autotuner on this workload (untimed, like a warm-up)
     plan = S.Plan()
+    tuning = {}
+    if not args.no_autotune:
+        tuning = plan.autotune(dp)
+        log("autotuned: %s" % tuning)
     for _ in range(args.warmup):
         d, g, f = plan.step(dp)
     torch.cuda.synchronize()
@@ -139,7 +145,7 @@ def run(args):
 
     # per-launch duration of the loop kernels: the same step run eagerly with
     # HIP events recorded by the library on this stream around every launch
-    tp = S.Plan(flags=S.TIMING)
+    tp = S.Plan(flags=S.TIMING, **tuning)
     tp.step(dp)
     torch.cuda.synchronize()
     tp.reset_timers()
@@ -151,7 +157,7 @@ def run(args):
 
     t_pt = value_pt = None
     if not args.no_per_task:
-        t_pt = per_task_step(S, dp, st["n_tiles"])
+        t_pt = per_task_step(S, dp, st["n_tiles"], tuning)
         value_pt = (P_d + P_f) / t_pt
         log("per-task launch step %.1f ms" % (t_pt * 1e3))
 
@@ -185,7 +191,8 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": "clustered 128^3: 2,097,152 particles, lognormal field "
                                "sigma_ln=1.5 on 64^3 grid, periodic unit box, FP32",
-                   "n": parts.n, "loops": "bin+density(Newton)+gradient+force"},
+                   "n": parts.n, "loops": "bin+density(Newton)+gradient+force",
+                   "tuning": tuning or "defaults"},
         "pairs": {"density": P_d, "gradient": P_g, "force": P_f},
         # per loop: useful pairs over the loop kernels' time per step (the
         # density loop runs its kernel once plus its fix-up passes)
@@ -212,6 +219,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default plan options instead of the autotuned ones")
     ap.add_argument("--no-per-task", action="store_true",
                     help="skip the per-task launch baseline (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

@@ -250,9 +250,9 @@ int swsph_step(swsph_plan* plan, const swsph_particles* p, swsph_density_out* d,
  * negative status (the stats are filled in either case). */
 int swsph_read_stats(swsph_plan* plan, const void* ws, swsph_stats* out, void* stream);
 
-/* Time the candidate tile sizes, LDS capacities and task orders on these
- * particles (runs bin + step several times, synchronises) and store the
- * fastest in the plan.  cache_path (nullable) names a text file used to
+/* Time the candidate tile sizes, LDS capacities, task orders and task-search
+ * leaf sizes on these particles (coordinate descent; runs bin + step several
+ * times, synchronises) and store the fastest in the plan.  cache_path (nullable) names a text file used to
  * reuse the choice across processes (key: device, n, n_box, dtype). */
 int swsph_autotune(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream,
                    const char* cache_path);
@@ -268,7 +268,6 @@ int swsph_kernel_times(swsph_plan* plan, double ms[4], uint64_t launches[4], voi
 /* Forget the recorded kernel timings. */
 int swsph_reset_timers(swsph_plan* plan);
 
-/* The tuning the plan will use: tile, lds_cap, order, leaf_max. */
 /* The execution options in effect (after defaults or swsph_autotune). */
 typedef struct swsph_tuning {
     int32_t tile, tile_dens, lds_cap, lds_cap_dens, order, leaf_max;

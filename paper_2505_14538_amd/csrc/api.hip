@@ -799,17 +799,19 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
             bool hit = false;
             while (std::fgets(line, sizeof line, f)) {
                 char k2[640];
-                int t = 0, td = 0, c = 0, cd = 0, o = 0;
+                int t = 0, td = 0, c = 0, cd = 0, o = 0, lm = 0;
                 auto tile_ok = [](int v) { return v == 8 || v == 16 || v == 32 || v == 64; };
                 auto cap_ok = [](int v) { return v == 128 || v == 256 || v == 512; };
-                if (std::sscanf(line, "%639s %d %d %d %d %d", k2, &t, &td, &c, &cd, &o) == 6 &&
+                if (std::sscanf(line, "%639s %d %d %d %d %d %d", k2, &t, &td, &c, &cd, &o, &lm) ==
+                        7 &&
                     std::strcmp(k2, key) == 0 && tile_ok(t) && tile_ok(td) && cap_ok(c) &&
-                    cap_ok(cd) && (o == 0 || o == 1)) {
+                    cap_ok(cd) && (o == 0 || o == 1) && lm >= 1 && lm <= 4096) {
                     pl->tile = t;
                     pl->tile_d = td;
                     pl->lds_cap = c;
                     pl->lds_cap_d = cd;
                     pl->order = o;
+                    pl->leaf_max = lm;
                     hit = true;
                 }
             }
@@ -832,13 +834,13 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
     hipEvent_t e0 = nullptr, e1 = nullptr;
     r = hip_check(hipEventCreate(&e0), "event");
     if (!r) r = hip_check(hipEventCreate(&e1), "event");
-    auto time_one = [&](int tile, int tile_d, int cap, int cap_d, int order,
-                        float& best_ms) -> int {
-        pl->tile = tile;
-        pl->tile_d = tile_d;
-        pl->lds_cap = cap;
-        pl->lds_cap_d = cap_d;
-        pl->order = order;
+    auto time_one = [&](const int (&w)[6], float& best_ms) -> int {
+        pl->tile = w[0];
+        pl->tile_d = w[1];
+        pl->lds_cap = w[2];
+        pl->lds_cap_d = w[3];
+        pl->order = w[4];
+        pl->leaf_max = w[5];
         float ms = 3.0e38f;
         for (int rep = 0; rep < 2; ++rep) {
             int q = hip_check(hipEventRecord(e0, s), "event record");
@@ -858,20 +860,22 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
         return SWSPH_OK;
     };
     // coordinate descent over the options: gradient/force tile size, density
-    // tile size, LDS capacities (gradient/force, density), task order
-    int v[5] = {pl->tile, pl->tile_d, pl->lds_cap, pl->lds_cap_d, pl->order};
+    // tile size, LDS capacities (gradient/force, density), task order, and
+    // the cell size at which the task search stops splitting
+    int v[6] = {pl->tile, pl->tile_d, pl->lds_cap, pl->lds_cap_d, pl->order, pl->leaf_max};
     float best = 3.0e38f;
-    if (!r) r = time_one(v[0], v[1], v[2], v[3], v[4], best);
+    if (!r) r = time_one(v, best);
     const int tiles[4] = {8, 16, 32, 64}, caps[3] = {128, 256, 512}, orders[2] = {0, 1};
-    const int* cand[5] = {tiles, tiles, caps, caps, orders};
-    const int ncand[5] = {4, 4, 3, 3, 2};
-    for (int d = 0; d < 5 && !r; ++d) {
+    const int leaves[3] = {16, 32, 64};
+    const int* cand[6] = {tiles, tiles, caps, caps, orders, leaves};
+    const int ncand[6] = {4, 4, 3, 3, 2, 3};
+    for (int d = 0; d < 6 && !r; ++d) {
         for (int k = 0; k < ncand[d] && !r; ++k) {
             if (cand[d][k] == v[d]) continue;
-            int w[5] = {v[0], v[1], v[2], v[3], v[4]};
+            int w[6] = {v[0], v[1], v[2], v[3], v[4], v[5]};
             w[d] = cand[d][k];
             float t = 0.f;
-            r = time_one(w[0], w[1], w[2], w[3], w[4], t);
+            r = time_one(w, t);
             if (!r && t < best) {
                 best = t;
                 v[d] = w[d];
@@ -885,10 +889,11 @@ int swsph_autotune(swsph_plan* pl, const swsph_particles* p, void* ws, void* str
     pl->lds_cap = v[2];
     pl->lds_cap_d = v[3];
     pl->order = v[4];
+    pl->leaf_max = v[5];
     if (r) return r;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d %d\n", key, v[0], v[1], v[2], v[3], v[4]);
+            std::fprintf(f, "%s %d %d %d %d %d %d\n", key, v[0], v[1], v[2], v[3], v[4], v[5]);
             std::fclose(f);
         }
     }

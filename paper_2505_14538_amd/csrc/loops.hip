@@ -111,6 +111,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     int ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, flushes, sweep);
     sweep(ns);
     const bool cached = flushes == 0;
+    T Rc = R;  // radius of the staged set
     for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
         ++iters;
         const T S0r = stream_sum(S0, q), S1r = stream_sum(S1, q);
@@ -156,17 +157,29 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
         H2 = act ? mul_unfused(H, H) : (T)-1;
         invH = (T)1 / H;
         zero();
+        // the staged set follows the sweep's largest support (the bounding-box
+        // distance never exceeds a lane's distance): a cached set is compacted
+        // in LDS when that support shrank and staged again from the list when
+        // h grew past it (it fit at R, so it fits at any smaller radius); a
+        // set that did not fit is staged again every sweep
+        const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
+        bool restage = !cached;
+        T Rs = Hs < R ? Hs : R;
         if (cached) {
-            sweep(ns);
-        } else {
-            // re-staging: only the supports of this sweep's h are needed
-            // (the bounding-box distance never exceeds a lane's distance)
-            const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
-            const T Rs = Hs < R ? Hs : R;
+            if (Hs > Rc) {
+                Rc = min(R, Hs * (T)1.05);
+                Rs = Rc;
+                restage = true;
+            } else if (Hs < (T)0.9 * Rc) {
+                Rc = Hs * (T)1.05;
+                ns = compact_staged(m, ns, g, Rc * Rc);
+            }
+        }
+        if (restage) {
             int fl = 0;
             ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, Rs * Rs, fl, sweep);
-            sweep(ns);
         }
+        sweep(ns);
     }
     S0 = stream_sum(S0, q);
     S1 = stream_sum(S1, q);

@@ -138,6 +138,41 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
     drain();
 }
 
+// Keep, in order and in place, the staged j-particles (two 4-vectors each,
+// the density loop's layout) whose distance to the tile box is below sqrt(R2) (staged positions already carry their periodic
+// image).  Writes never pass the chunk being read, so in place is safe.
+// Returns the new count.
+template <typename T, int CAP>
+__device__ int compact_staged(WaveMem<T, CAP, 2>& m, int ns, const TileGeom& g, T R2) {
+    const int lane = lane_id();
+    int out = 0;
+    for (int b = 0; b < ns; b += WAVE) {
+        const int k = b + lane;
+        const bool have = k < ns;
+        V4<T> s0{}, s1{};
+        bool keep = false;
+        if (have) {
+            s0 = m.s[0][k];
+            s1 = m.s[1][k];
+            const T x = s0.x, y = s0.y, z = s0.z;
+            const T gx = max((T)0, max((T)g.lo[0] - x, x - (T)g.hi[0]));
+            const T gy = max((T)0, max((T)g.lo[1] - y, y - (T)g.hi[1]));
+            const T gz = max((T)0, max((T)g.lo[2] - z, z - (T)g.hi[2]));
+            keep = dist2_unfused(gx, gy, gz) < R2;
+        }
+        const unsigned long long km = ballot(keep);
+        wave_sync();
+        if (keep) {
+            const int o = out + mbcnt(km);
+            m.s[0][o] = s0;
+            m.s[1][o] = s1;
+        }
+        out += __popcll(km);
+        wave_sync();
+    }
+    return out;
+}
+
 // loop kinds: forward loops and the three pair passes of the adjoint
 enum { L_DENS = 0, L_GRAD = 1, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
 
