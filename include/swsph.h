@@ -214,7 +214,11 @@ int swsph_bin(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream
 int swsph_density(swsph_plan* plan, const swsph_particles* p, swsph_density_out* o,
                   void* ws, void* stream);
 
-/* Gradient loop (Sec. 2.1.3) at the density results d. */
+/* Gradient loop (Sec. 2.1.3) at the density results d.  The gradient and
+ * force loops run in one kernel (one task build, one staging, one pass of
+ * distance tests): this call and swsph_force each run it and copy out their
+ * own outputs, and swsph_step runs it once for both; all three give the
+ * same bits. */
 int swsph_gradient(swsph_plan* plan, const swsph_particles* p,
                    const swsph_density_out* d, swsph_gradient_out* o, void* ws,
                    void* stream);
@@ -259,8 +263,8 @@ int swsph_autotune(swsph_plan* plan, const swsph_particles* p, void* ws, void* s
 
 /* Per-launch duration of the loop kernels, from HIP events the library
  * records on the call's stream around each loop-kernel launch when the plan
- * has SWSPH_TIMING (index 0 density, 1 gradient, 2 force, 3 backward pair
- * passes).  ms[k] = mean milliseconds per launch, launches[k] = launches
+ * has SWSPH_TIMING (index 0 density, 2 the joint gradient and force loop,
+ * 3 backward pair passes; index 1 is no longer used and stays 0).  ms[k] = mean milliseconds per launch, launches[k] = launches
  * timed since the last reset.  Synchronises the stream.  Without
  * SWSPH_TIMING every entry is 0. */
 int swsph_kernel_times(swsph_plan* plan, double ms[4], uint64_t launches[4], void* stream);

@@ -519,7 +519,9 @@ int swsph_density(swsph_plan* pl, const swsph_particles* p, swsph_density_out* o
 namespace {
 
 // Gradient and/or force over one density result: the density fields are
-// gathered into binned order and the task lists built once for both loops.
+// gathered into binned order, the task lists built, and one loop kernel
+// computes both loops (the outputs asked for are copied out), so the
+// separate calls and the joint one give the same bits.
 template <typename T>
 int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
                swsph_gradient_out* go, swsph_force_out* fo, void* ws, hipStream_t s) {
@@ -530,15 +532,13 @@ int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out
     (void)p;
     launch_prep_dens<T>(b, sc, d, s);
     launch_gf_tasks<T>(b, sc, s);
+    if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
+        return fail(SWSPH_E_HIP, "gradient/force kernel launch failed");
     if (go) {
-        if (launch_gradient<T>(b, sc, mode, pl->lds_cap, s))
-            return fail(SWSPH_E_HIP, "gradient kernel launch failed");
         launch_unsort<T>(n, b.rank, (T*)b.g_out, go->v_sig, s);
         launch_unsort<T>(n, b.rank, (T*)b.g_out + n, go->lap_u, s);
     }
     if (fo) {
-        if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
-            return fail(SWSPH_E_HIP, "force kernel launch failed");
         void* dst[4] = {fo->ax, fo->ay, fo->az, fo->dudt};
         for (int k = 0; k < 4; ++k) launch_unsort<T>(n, b.rank, (T*)b.f_out + k * n, dst[k], s);
         if (fo->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, fo->nint, s);

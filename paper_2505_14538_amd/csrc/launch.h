@@ -96,11 +96,10 @@ void launch_prep_dens(const BinPtrs& b, const Scheme& sc, const swsph_density_ou
                       hipStream_t s);
 template <typename T>
 void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s);
-// The task lists both loops below read (build before either).
+// The task lists of the loop below (build first).
 template <typename T>
 void launch_gf_tasks(const BinPtrs& b, const Scheme& sc, hipStream_t s);
-template <typename T>
-int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
+// The gradient and the force loop in one kernel (binned outputs g_out, f_out).
 template <typename T>
 int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
 template <typename T>

@@ -240,84 +240,12 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     ws.failed += (unsigned long long)__popcll(fmask);
 }
 
-// ----------------------------------------------------------- gradient tile
-
-template <typename T, int CAP>
-__device__ void gradient_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t, WaveStats& ws) {
-    Tile tl = a.tiles[t];
-    tl.begin = uniform(tl.begin);
-    tl.count = uniform(tl.count);
-    tl.box = uniform(tl.box);
-    if (tl.count <= 0) return;
-    const int lane = lane_id();
-    const LaneMap q = lane_map(tl.count);
-    const int js = q.js, S = q.S;
-    const bool act = q.used();
-    const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? q.li : 0);
-    const BoxInfo bi = a.boxtab[tl.box];
-    const V4<T> pi = a.pos4[i];
-    const V4<T> vi = a.vel4[i];
-    const V4<T> di = a.dens4[i];
-    const T h = a.hs[i];
-    const TileGeom g = geom_of(tl);
-    const T eps = a.eps;
-    const T H = mul_unfused(eps, h);
-    const T H2 = act ? mul_unfused(H, H) : (T)-1;
-    const T invH = (T)1 / H;
-    // the tile's own radius, formed as a gradient-only task build forms it
-    // (the list comes from the force build, whose radius is never smaller)
-    const T hmax = wave_max(act ? h : (T)0);
-    const T Rg = (T)(float)(eps * hmax * (T)(1 + 4e-7));
-    const T Rt = (T)a.trad[t];
-    const T R = Rg < Rt ? Rg : Rt;
-    const T ci = di.z, ui = vi.w;
-    T vsig = (T)2 * ci, lap = 0;
-    unsigned long long tested = 0;
-    int inside = 0;
-    auto test = [&](int k, bool ok) {
-        const V4<T> sj = m.s[0][k];
-        const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        return ok && r2 < H2 && r2 > (T)0;
-    };
-    auto body = [&](int k) {
-        const V4<T> sj = m.s[0][k];
-        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
-        const T r2 = dist2_unfused(dx, dy, dz);
-        const V4<T> vj = m.s[1][k];
-        const T uj = m.s[2][k].x;
-        const T inv_r = fast_rsqrt(r2);
-        const T q = r2 * inv_r * invH;
-        const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
-        const T mu = vr < (T)0 ? vr * inv_r : (T)0;
-        const T s = ci + vj.w - a.beta * mu;
-        vsig = s > vsig ? s : vsig;
-        const T t1 = (T)1 - q;
-        const T gin = (T)18 * q - (T)12, gout = (T)-6 * t1 * t1 * (H * inv_r);
-        const T gq = q < (T)0.5 ? gin : gout;
-        lap += sj.w * (ui - uj) * gq;
-        ++inside;
-    };
-    auto sweep = [&](int ns) {
-        pair_loop(m, ns, js, S, test, body);
-        tested += (unsigned long long)ns;
-    };
-    int flushes = 0;
-    const int ns = stage_tile<L_GRAD, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
-    sweep(ns);
-    vsig = stream_max(vsig, q);
-    lap = stream_sum(lap, q);
-    inside = stream_sum(inside, q);
-    if (lead) {
-        const T k5 = (T)(8.0 / PI_D) * invH * invH * invH * invH * invH;
-        a.out[0 * a.n + i] = vsig;
-        a.out[1 * a.n + i] = (T)2 * k5 * lap;
-    }
-    ws.inside += (unsigned long long)wave_sum(lead ? inside : 0);
-    ws.tested += tested * (unsigned long long)tl.count;
-}
-
-// -------------------------------------------------------------- force tile
+// ------------------------------------------------- gradient and force tile
+// One staging and one pass of distance tests serve both loops: the force
+// hits (r < max(H_i, H_j), Eq. 17-18) contain the gradient pairs (r < H_i,
+// Eq. 10-11, 13), whose terms are added where r < H_i.  The gradient loop's
+// outputs do not feed the force loop (alpha is constant, and the pairwise
+// signal speed enters Eq. 9), so nothing orders the two.
 
 template <typename T, int CAP>
 __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, WaveStats& ws) {
@@ -350,6 +278,9 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
     const T alpha = a.alpha, beta = a.beta;
     T ax = 0, ay = 0, az = 0, du = 0;
     int nint = 0;
+    const T ui = vi.w;
+    T vsig = (T)2 * ci, lap = 0;  // gradient loop
+    int ginside = 0;
     unsigned long long tested = 0;
     // hits: every j (self included) with r < max(H_i, H_j); the self pair and
     // coincident pairs (r = 0) add nothing to a and du/dt, so only r > 0 goes
@@ -369,20 +300,27 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
         const T H2j = sj.w;
         const V4<T> vj = m.s[1][k];
         const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
-        const T rhoj = m.s[3][k].x;
+        const V4<T> ej = m.s[3][k];  // (rho_j, j, u_j, m_j / rho_j)
+        const T rhoj = ej.x;
         const T inv_r = fast_rsqrt(r2);
         const T r = r2 * inv_r;
-        const T gi = r2 < H2 ? kgi * m4_dw(r * invH) : (T)0;
+        const bool gin = r2 < H2;  // inside the support of i: a gradient pair
+        const T gi = gin ? kgi * m4_dw(r * invH) : (T)0;
         const T ihj = cj.w;
         const T gj = r2 < H2j ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
         const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
         const T vdote = vr * inv_r;
+        const T mu = vdote < (T)0 ? vdote : (T)0;
+        const T vs = ci + vj.w - beta * mu;
         T nu = 0;
-        if (visc) {
-            const T mu = vdote < (T)0 ? vdote : (T)0;
-            const T vs = ci + vj.w - beta * mu;
-            nu = -alpha * mu * vs / (rhoi + rhoj);
-        }
+        if (visc) nu = -alpha * mu * vs / (rhoi + rhoj);
+        // gradient loop: signal speed and the Laplacian of u
+        const T q = r * invH;
+        const T t1 = (T)1 - q;
+        const T gq = q < (T)0.5 ? (T)18 * q - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
+        vsig = gin && vs > vsig ? vs : vsig;
+        lap += gin ? ej.w * (ui - ej.z) * gq : (T)0;
+        ginside += gin ? 1 : 0;
         const T mfg = cj.x * fi * gi + cj.z * gj;
         const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
         const T sr = sa * inv_r;
@@ -403,14 +341,21 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
     az = stream_sum(az, q);
     du = stream_sum(du, q);
     nint = stream_sum(hits, q) - 1;
+    vsig = stream_max(vsig, q);
+    lap = stream_sum(lap, q);
+    ginside = stream_sum(ginside, q);
     if (lead) {
         a.out[0 * a.n + i] = ax;
         a.out[1 * a.n + i] = ay;
         a.out[2 * a.n + i] = az;
         a.out[3 * a.n + i] = du;
         a.iout[i] = nint;
+        const T k5 = cn * invH * invH * invH * invH * invH;
+        a.gout[0 * a.n + i] = vsig;
+        a.gout[1 * a.n + i] = (T)2 * k5 * lap;
     }
     ws.inside += (unsigned long long)wave_sum(lead ? nint : 0);
+    ws.inside_g += (unsigned long long)wave_sum(lead ? ginside : 0);
     ws.tested += tested * (unsigned long long)tl.count;
 }
 
@@ -419,7 +364,6 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
 template <int LK, typename T, int CAP>
 __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, WaveStats& ws) {
     if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t, ws);
-    else if (LK == L_GRAD) gradient_tile<T, CAP>(*(WaveMem<T, CAP, 3>*)wm, a, t, ws);
     else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
@@ -514,28 +458,18 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     }
     return r;
 }
-// Task lists of the gradient and force loops: one build serves both.  The
-// force list (support max(H_i, H_j)) contains every pair the gradient loop
-// needs (support H_i); the gradient loop culls it to its own radius while
-// staging, which leaves exactly the set a gradient-only search would list.
+// Task lists of the joint gradient/force loop: the force list (support
+// max(H_i, H_j)) contains every pair the gradient loop needs (support H_i).
 template <typename T>
 void launch_gf_tasks(const BinPtrs& b, const Scheme& sc, hipStream_t s) {
     launch_hmax_pyramid<T>(b, sc, s);
     launch_tasks<T>(b, sc, 2, false, s);
 }
 template <typename T>
-int launch_gradient(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
-    KArgs<T> a = make_args<T>(b, sc);
-    a.out = (T*)b.g_out;
-    timer_begin(sc.timer, 1, s);
-    const int r = launch_loop<L_GRAD, T>(a, mode, lds_cap, 1, s);
-    timer_end(sc.timer, 1, s);
-    return r;
-}
-template <typename T>
 int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
     KArgs<T> a = make_args<T>(b, sc);
     a.out = (T*)b.f_out;
+    a.gout = (T*)b.g_out;
     a.iout = b.f_int;
     timer_begin(sc.timer, 2, s);
     const int r = launch_loop<L_FORCE, T>(a, mode, lds_cap, 2, s);
@@ -547,8 +481,6 @@ template int launch_density<float>(const BinPtrs&, const Scheme&, int, int, hipS
 template int launch_density<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template void launch_gf_tasks<float>(const BinPtrs&, const Scheme&, hipStream_t);
 template void launch_gf_tasks<double>(const BinPtrs&, const Scheme&, hipStream_t);
-template int launch_gradient<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
-template int launch_gradient<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_force<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_force<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 

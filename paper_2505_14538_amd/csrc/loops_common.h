@@ -37,6 +37,7 @@ struct KArgs {
     const V4<T>* dens4;
     const V4<T>* aux4;         // adjoint passes: per-particle staging data
     T* out;                    // sorted outputs, arrays of n
+    T* gout;                   // joint gradient/force loop: the gradient outputs
     int32_t* iout;             // sorted int outputs, arrays of n
     int64_t n;
     Counters* cnt;
@@ -174,11 +175,11 @@ __device__ int compact_staged(WaveMem<T, CAP, 2>& m, int ns, const TileGeom& g, 
 }
 
 // loop kinds: forward loops and the three pair passes of the adjoint
-enum { L_DENS = 0, L_GRAD = 1, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
+// (1 is unused: the gradient loop runs inside the force loop kernel)
+enum { L_DENS = 0, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
 
 template <int LK> struct LoopNV;
 template <> struct LoopNV<L_DENS> { static constexpr int NV = 2; };
-template <> struct LoopNV<L_GRAD> { static constexpr int NV = 3; };
 template <> struct LoopNV<L_FORCE> { static constexpr int NV = 4; };
 template <> struct LoopNV<L_ADJA> { static constexpr int NV = 5; };
 template <> struct LoopNV<L_ADJC> { static constexpr int NV = 2; };
@@ -203,7 +204,7 @@ template <int LK, typename T>
 __device__ __forceinline__ void gather_j(const KArgs<T>& a, int j, JData<LK, T>& r) {
     r.p = a.pos4[j];
     if (LK <= L_ADJA) r.v = a.vel4[j];
-    if (LK == L_GRAD || LK == L_FORCE || LK == L_ADJA) r.d = a.dens4[j];
+    if (LK == L_FORCE || LK == L_ADJA) r.d = a.dens4[j];
     if (LK >= L_ADJA) r.x = a.aux4[j];
     if (Symmetric<LK>::value) r.h = a.hs[j];
 }
@@ -267,18 +268,13 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
             if (LK == L_DENS) {
                 m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
-            } else if (LK == L_GRAD) {
-                const V4<T> da = r.d;  // (rho, f, c, A)
-                m.s[0][k] = V4<T>{xs, ys, zs, pa.w / da.x};
-                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                m.s[2][k] = V4<T>{va.w, (T)0, (T)0, (T)0};
             } else if (LK == L_FORCE) {
                 const V4<T> da = r.d;
                 const T Hj = mul_unfused(a.eps, r.h);
                 m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
                 m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
                 m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
-                m.s[3][k] = V4<T>{da.x, int_as<T>(j), (T)0, (T)0};
+                m.s[3][k] = V4<T>{da.x, int_as<T>(j), va.w, pa.w / da.x};
             } else if (LK == L_ADJA) {
                 const V4<T> da = r.d;   // (rho, f, c, A)
                 const V4<T> wj = r.x;   // (dL/dax, dL/day, dL/daz, dL/ddu)
@@ -354,6 +350,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.dens4 = (const V4<T>*)b.dens4;
     a.aux4 = nullptr;
     a.out = nullptr;
+    a.gout = nullptr;
     a.iout = nullptr;
     a.n = b.n;
     a.cnt = b.cnt;
@@ -377,10 +374,15 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
 // atomic counters).
 struct WaveStats {
     unsigned long long tested = 0, inside = 0, sweeps = 0, smax = 0, failed = 0, restages = 0;
+    unsigned long long inside_g = 0;  // gradient pairs of the joint gradient/force loop
     __device__ void flush(Counters* c, int loop) const {
         if (lane_id() != 0) return;
         if (tested) atomicAdd(&c->pairs_tested[loop], tested);
         if (inside) atomicAdd(&c->pairs_inside[loop], inside);
+        if (loop == L_FORCE) {
+            if (tested) atomicAdd(&c->pairs_tested[LOOP_GRADIENT], tested);
+            if (inside_g) atomicAdd(&c->pairs_inside[LOOP_GRADIENT], inside_g);
+        }
         if (sweeps) atomicAdd(&c->newton_sweeps, sweeps);
         if (smax) atomicMax(&c->newton_max, smax);
         if (failed) atomicAdd(&c->newton_failed, failed);

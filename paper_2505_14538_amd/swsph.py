@@ -378,11 +378,12 @@ class Plan:
         return d
 
     def kernel_times(self) -> Dict[str, Dict[str, float]]:
-        """Mean ms per launch of each loop kernel (plan created with TIMING)."""
+        """Mean ms per launch of each loop kernel (plan created with TIMING);
+        the gradient and force loops share one kernel ("gradient+force")."""
         ms = (ctypes.c_double * 4)()
         n = (ctypes.c_uint64 * 4)()
         _check(_lib.swsph_kernel_times(self.h, ms, n, _stream()))
-        names = ("density", "gradient", "force", "backward")
+        names = ("density", "gradient", "gradient+force", "backward")
         return {names[k]: {"ms": ms[k], "launches": int(n[k])} for k in range(4) if n[k] > 0}
 
     def reset_timers(self):
