@@ -32,14 +32,47 @@ sys.path.insert(0, ROOT)
 # pair inside the support (FMA = 2, add/mul/min/max = 1, sqrt/rsqrt/rcp = 1).
 F_DENS = 55.0     # full density sums (n, dn/dh, rho, drho/dh, div v, curl v)
 F_NEWTON = 25.0   # each additional Newton sweep (n and dn/dh only)
-F_GRAD = 33.0
+F_GRAD = 33.0     # the gradient loop on its own
 F_FORCE = 67.0
+F_GRAD_JOINT = 17.0  # a gradient pair inside the joint gradient/force body
+                     # (distance, 1/r, v.r and the signal speed shared with force)
 PEAK_FP32 = 157.3e12   # MI355X published FP32 vector peak (packed FMA)
 PEAK_HBM = 8.0e12
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clustered_128cubed.json")
+
+
+def sources_digest():
+    """sha256 over the library's kernel sources (csrc/*.hip, *.h), sorted by name."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_14538_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None
+    when the kernel sources changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_dispatch")
 
 
 def cpu_baseline(parts):
@@ -117,6 +150,7 @@ def run(args):
     # options (tile sizes, LDS capacities, task order) from the library's
     # autotuner on this workload (untimed, like a warm-up)
     plan = S.Plan()
+    defaults = plan.tuning()
     tuning = {}
     if not args.no_autotune:
         tuning = plan.autotune(dp)
@@ -139,7 +173,7 @@ def run(args):
     P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
     sweeps = st["newton_sweeps"] / max(1, st["n_tiles_dens"])   # counters cover the last step
     value = (P_d + P_f) / t_step
-    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD + P_f * F_FORCE
+    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD_JOINT + P_f * F_FORCE
     frac_peak = flops / t_step / PEAK_FP32
     log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
 
@@ -170,10 +204,14 @@ def run(args):
     k_ms = kt[dom]["ms"]
     per_step = kt[dom]["launches"] / args.steps
     per_launch_flops = {"density": P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON),
-                        "gradient+force": P_g * F_GRAD + P_f * F_FORCE}[dom] / per_step
+                        "gradient+force": P_g * F_GRAD_JOINT + P_f * F_FORCE}[dom] / per_step
     achieved = per_launch_flops / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12), "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12),
+                # counters were taken with the default options
+                "traffic": measured_traffic({"density": "k_loop<0",
+                                             "gradient+force": "k_loop<2"}[dom])
+                           if not tuning or tuning == defaults else None,
                 "kernel": "k_loop<%s> (loop kernel of the %s loop)" % (dom, dom),
                 "kernel_ms": k_ms}
     res = {
