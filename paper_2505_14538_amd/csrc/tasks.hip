@@ -76,16 +76,19 @@ __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_
     while (2 * top <= nl) top *= 2;
     for (int v0 = 0; v0 < nv; v0 += CAND_U * WAVE) {
         // leaf of slot v: the last leaf whose prefix is <= v (prefixes rise
-        // strictly, lpre[0] = 0), by binary lifting with a uniform step count
-        // so the slots' LDS reads overlap
+        // strictly, lpre[0] = 0, lpre[nl..2 WAVE] = the total), by binary
+        // lifting with a uniform step count so the slots' LDS reads overlap
         int lo[CAND_U];
 #pragma unroll
         for (int u = 0; u < CAND_U; ++u) lo[u] = 0;
         for (int st = top; st > 0; st >>= 1) {
+            // unconditional reads (no branch around them, so they overlap):
+            // prefixes from nl on equal the total and never pass the test
 #pragma unroll
             for (int u = 0; u < CAND_U; ++u) {
                 const int c = lo[u] + st;
-                if (c < nl && lpre[c] <= v0 + u * WAVE + lane) lo[u] = c;
+                const int cr = c < 2 * WAVE ? c : 2 * WAVE;
+                lo[u] = lpre[cr] <= v0 + u * WAVE + lane ? c : lo[u];
             }
         }
         int jj[CAND_U], cc[CAND_U];
@@ -391,7 +394,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
             for (int d = 0; d < 3; ++d) { blo[d] = tm.lo[d]; bhi[d] = tm.hi[d]; }
         }
         float Rl = 0.f;
-        int moff = 0;
+        int moff = 0, gend = 0;
         const int pc = uniform(tp.count);
         const int pb = uniform(tp.begin);
         const T h = lane < pc ? a.hs[pb + lane] : (T)0;
@@ -454,7 +457,8 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                             zs = pa.z + (T)sz * Lt;
                             ent = (uint32_t)j | ((uint32_t)code << 26);
                         }
-                        for (int c = 0; c < nd; ++c) {
+                        // member c's test (its box and radius read from lane c)
+                        auto inside = [&](int c) {
                             const T r2c = lane_val(R2c, c);
                             const T lx = (T)lane_val(blo[0], c), hx = (T)lane_val(bhi[0], c);
                             const T ly = (T)lane_val(blo[1], c), hy = (T)lane_val(bhi[1], c);
@@ -462,15 +466,23 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                             const T gx = max((T)0, max(lx - xs, xs - hx));
                             const T gy = max((T)0, max(ly - ys, ys - hy));
                             const T gz = max((T)0, max(lz - zs, zs - hz));
-                            const bool pass_c = have && dist2_unfused(gx, gy, gz) < r2c;
-                            const unsigned long long pm = ballot(pass_c);
-                            const int run_c = lane_val(run, c);
-                            const int off_c = lane_val(moff, c);
-                            if (pass == 1 && pass_c) {
-                                const int64_t at = (int64_t)off_c + run_c + mbcnt(pm);
-                                if (at < a.cand_cap) a.cands[at] = ent;
+                            return have && dist2_unfused(gx, gy, gz) < r2c;
+                        };
+                        if (pass == 0) {
+                            // counting pass: sizes only
+                            for (int c = 0; c < nd; ++c) {
+                                const unsigned long long pm = ballot(inside(c));
+                                if (lane == c) run += __popcll(pm);
                             }
-                            if (lane == c) run += __popcll(pm);
+                        } else {
+                            // filling pass (gend: end of the group's space)
+                            for (int c = 0; c < nd; ++c) {
+                                const bool pass_c = inside(c);
+                                const unsigned long long pm = ballot(pass_c);
+                                const int at = lane_val(moff, c) + lane_val(run, c) + mbcnt(pm);
+                                if (pass_c && at < gend) a.cands[at] = ent;
+                                if (lane == c) run += __popcll(pm);
+                            }
                         }
                     });
                     st.nleaf = 0;
@@ -488,6 +500,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Til
                 base = __shfl(base, 0, WAVE);
                 const bool fits = base + tot <= a.cand_cap;
                 if (!fits && lane == 0) latch(a.cnt, SWSPH_ST_CAPACITY);
+                gend = (int)(base + tot);
                 if (lane < nd) {
                     moff = (int32_t)(base + e);
                     a.cand_off[d0 + lane] = fits ? (int32_t)(base + e) : -1;
