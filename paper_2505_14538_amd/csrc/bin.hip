@@ -233,7 +233,8 @@ void launch_scatter_stable(int64_t n, const uint32_t* keys, const int32_t* slot,
 
 // Sorted copies: pos4 = (x, y, z, m), vel4 = (vx, vy, vz, u), hs = h guess.
 // Without a guess, h0 = eta * w_l / cbrt(N_l) from the first enclosing cell
-// (walking up from the fine cell) that holds at least 16 particles.
+// (walking up from the fine cell) that holds at least 16 particles, blended
+// with the child cell's estimate where that cell holds more than 32.
 template <typename T>
 __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
                          const T* __restrict__ z, const T* __restrict__ vx,
@@ -260,17 +261,27 @@ __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict
         uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
         const int k = bi.k < 10 ? bi.k : 10;
         int lev = k;
-        int64_t cntl = 0;
+        int64_t cntl = 0, child = 0;
         for (; lev >= 0; --lev) {
             int sh = 3 * (k - lev);
             int64_t beg = bi.fine_off + (int64_t)((mort >> sh) << sh);
             int64_t end = beg + (int64_t(1) << sh);
+            child = cntl;
             cntl = cstart[end] - cstart[beg];
             if (cntl >= 16) break;
         }
         if (lev < 0) lev = 0;
         double w = bi.L / (double)(1 << lev);
-        h = (T)(eta * w / cbrt((double)(cntl > 0 ? cntl : 1)));
+        double hg = eta * w / cbrt((double)(cntl > 0 ? cntl : 1));
+        if (cntl > 32 && lev < k) {
+            // the enclosing cell is much fuller than the particle's own
+            // (a clump elsewhere in it): meet the estimate of the child cell
+            // half way (geometric mean), which halves the tiles whose root
+            // lies beyond their staged neighbourhood
+            const double hc = eta * 0.5 * w / cbrt((double)(child > 0 ? child : 1));
+            hg = sqrt(hg * hc);
+        }
+        h = (T)hg;
     }
     hs[s] = h;
 }
@@ -354,38 +365,33 @@ __global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict_
     tiles[tidx[s]] = tl;
 }
 
-// One wavefront per tile (grid-stride over the device tile count): the
-// bounding box and largest h of its particles.
+// The bounding box and largest h of each tile's particles.
 template <typename T>
 __global__ void k_tile_bounds(const V4<T>* __restrict__ pos4, const T* __restrict__ hs,
                               Tile* __restrict__ tiles, int32_t* __restrict__ order,
                               const unsigned long long* __restrict__ ntiles) {
+    // one thread per tile (a tile holds at most 64 consecutive particles;
+    // min and max are exact in any order)
     const int64_t nt = (int64_t)*ntiles;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t t = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; t < nt;
-         t += nw) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += stride) {
         Tile tl = tiles[t];
-        const bool act = lane < tl.count;
-        float px = 0, py = 0, pz = 0, h = 0;
-        if (act) {
-            const V4<T> a = pos4[tl.begin + lane];
-            px = (float)a.x; py = (float)a.y; pz = (float)a.z;
-            h = (float)hs[tl.begin + lane];
+        float lx = 3.0e38f, ly = 3.0e38f, lz = 3.0e38f;
+        float ux = -3.0e38f, uy = -3.0e38f, uz = -3.0e38f, hm = 0.0f;
+        const int cnt = tl.count < 64 ? tl.count : 64;
+        for (int k = 0; k < cnt; ++k) {
+            const V4<T> a = pos4[tl.begin + k];
+            const float px = (float)a.x, py = (float)a.y, pz = (float)a.z;
+            lx = fminf(lx, px); ly = fminf(ly, py); lz = fminf(lz, pz);
+            ux = fmaxf(ux, px); uy = fmaxf(uy, py); uz = fmaxf(uz, pz);
+            hm = fmaxf(hm, (float)hs[tl.begin + k]);
         }
-        const float lx = wave_min(act ? px : 3.0e38f), ly = wave_min(act ? py : 3.0e38f),
-                    lz = wave_min(act ? pz : 3.0e38f);
-        const float ux = wave_max(act ? px : -3.0e38f), uy = wave_max(act ? py : -3.0e38f),
-                    uz = wave_max(act ? pz : -3.0e38f);
-        const float hm = wave_max(act ? h : 0.0f);
-        if (lane == 0) {
-            tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;
-            tl.hi[0] = ux; tl.hi[1] = uy; tl.hi[2] = uz;
-            tl.hmax = hm;
-            tl.cost = (float)tl.count;
-            tiles[t] = tl;
-            order[t] = (int32_t)t;
-        }
+        tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;
+        tl.hi[0] = ux; tl.hi[1] = uy; tl.hi[2] = uz;
+        tl.hmax = hm;
+        tl.cost = (float)tl.count;
+        tiles[t] = tl;
+        order[t] = (int32_t)t;
     }
 }
 
@@ -406,7 +412,7 @@ static void make_tile_set(const BinPtrs& b, int32_t tile, Tile* tiles, int32_t* 
     launch_exclusive_scan(b.slot, b.n, b.scan_part, b.tmpidx, s);
     hipLaunchKernelGGL(k_tile_make, dim3(g), dim3(256), 0, s, b.n, b.n_box, b.boxtab, b.keys,
                        b.perm, b.cstart, tile, b.slot, b.tmpidx, tiles, ntiles);
-    hipLaunchKernelGGL(k_tile_bounds<T>, dim3(wave_grid(b.tile_cap, 4)), dim3(4 * WAVE), 0, s,
+    hipLaunchKernelGGL(k_tile_bounds<T>, dim3((unsigned)((b.tile_cap + 255) / 256)), dim3(256), 0, s,
                        (const V4<T>*)b.pos4, (const T*)b.hs, tiles, order,
                        (const unsigned long long*)ntiles);
 }
