@@ -135,7 +135,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.order = take(4 * (uint64_t)toff);
     l.tiles_d = take(sizeof(Tile) * (uint64_t)toff);
     l.order_d = take(4 * (uint64_t)toff);
-    l.dfirst = take(4 * (uint64_t)(toff + 1));
+    l.dparent = take(4 * (uint64_t)(toff + 1));
     l.ord_table = take(4 * (uint64_t)order_table_size(toff));
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.cand_cnt = take(4 * (uint64_t)(toff + 1));
@@ -296,7 +296,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     const bool same = pl->G.tile_d == pl->G.tile;
     b.tiles_d = same ? b.tiles : (Tile*)(w + l.tiles_d);
     b.order_d = same ? b.order : (int32_t*)(w + l.order_d);
-    b.dfirst = (int32_t*)(w + l.dfirst);
+    b.dparent = (int32_t*)(w + l.dparent);
     b.ord_table = (int32_t*)(w + l.ord_table);
     b.ord_base = (int32_t*)(w + l.ord_base);
     b.cand_cnt = (int32_t*)(w + l.cand_cnt);

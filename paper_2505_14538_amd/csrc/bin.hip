@@ -417,27 +417,17 @@ static void make_tile_set(const BinPtrs& b, int32_t tile, Tile* tiles, int32_t* 
                        (const unsigned long long*)ntiles);
 }
 
-// Groups of density tiles: dfirst[p] = first density tile inside
-// gradient/force tile p (cells nest and an overfull finest cell is cut in
-// order, so each density tile lies in one gradient/force tile and the
-// members of a group are consecutive); dfirst[n_tiles] = n_tiles_d.  From
-// the flags and exclusive scan of the gradient/force tile set.
-__global__ void k_dgroups(const Tile* __restrict__ tiles_d, const unsigned long long* __restrict__ ntd,
-                          const unsigned long long* __restrict__ ntg,
+// Parent of each density tile: the gradient/force tile containing its
+// particles (cells nest, and both sets follow the same Morton order), read
+// from the gradient/force tile scan at the tile's first particle.
+__global__ void k_dparent(const Tile* __restrict__ tiles_d, const unsigned long long* __restrict__ ntd,
                           const int32_t* __restrict__ flag, const int32_t* __restrict__ tidx,
-                          int32_t* __restrict__ dfirst) {
+                          int32_t* __restrict__ dparent) {
     const int64_t nt = (int64_t)*ntd;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += nth) {
         const int32_t s = tiles_d[t].begin;
-        const int32_t p = tidx[s] + flag[s] - 1;
-        int32_t q = -1;
-        if (t > 0) {
-            const int32_t s1 = tiles_d[t - 1].begin;
-            q = tidx[s1] + flag[s1] - 1;
-        }
-        if (p != q) dfirst[p] = (int32_t)t;
-        if (t == nt - 1) dfirst[*ntg] = (int32_t)nt;
+        dparent[t] = tidx[s] + flag[s] - 1;
     }
 }
 
@@ -449,10 +439,9 @@ void launch_make_tiles(const BinPtrs& b, hipStream_t s) {
         make_tile_set<T>(b, b.tile, b.tiles, b.order, &b.cnt->n_tiles, s);
         // groups need density tiles inside gradient/force tiles: smaller ones
         if (b.tile_d < b.tile)
-            hipLaunchKernelGGL(k_dgroups, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_dparent, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
                                (const Tile*)b.tiles_d, (const unsigned long long*)&b.cnt->n_tiles_d,
-                               (const unsigned long long*)&b.cnt->n_tiles, (const int32_t*)b.slot,
-                               (const int32_t*)b.tmpidx, b.dfirst);
+                               (const int32_t*)b.slot, (const int32_t*)b.tmpidx, b.dparent);
     } else {
         make_tile_set<T>(b, b.tile, b.tiles, b.order, &b.cnt->n_tiles, s);
         launch_copy_u64(&b.cnt->n_tiles_d, &b.cnt->n_tiles, s);

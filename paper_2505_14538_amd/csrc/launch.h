@@ -6,6 +6,10 @@
 
 namespace swsph {
 
+// Density task lists reach this factor beyond the largest guessed support of
+// their tile (the Newton iteration's room before a fix-up pass).
+constexpr double DENS_MARGIN = 1.25;
+
 // Events around loop-kernel launches (SWSPH_TIMING); owned by the plan.
 struct Timer;
 void timer_begin(Timer* t, int loop, hipStream_t s);
@@ -35,7 +39,7 @@ struct BinPtrs {
     unsigned long long* ntiles;  // its device count
     Tile* tiles_d;             // density tiles (may alias tiles)
     int32_t* order_d;
-    int32_t* dfirst;           // first density tile of each gradient/force tile (+ end)
+    int32_t* dparent;          // gradient/force tile containing each density tile
     int32_t *ord_table, *ord_base;  // cost-order sort: class x block counts, their scan
     int32_t *cand_cnt, *cand_off;
     uint32_t* cands;
@@ -83,8 +87,6 @@ void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, 
 // tasks.hip: mode 0 density, 1 gradient, 2 force; fixup: only flagged tiles
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s);
-template <typename T>
-void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s);
 void launch_order(const BinPtrs& b, hipStream_t s);
 int64_t order_table_size(int64_t tile_cap);
 

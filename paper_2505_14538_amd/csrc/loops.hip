@@ -52,7 +52,25 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     // root of sum_j w(q_ij) = Tt  <=>  h^3 n(h) = eta^3
     const T Tt = a.eta * a.eta * a.eta * eps * eps * eps / cnorm;
     const T tiny = (sizeof(T) == 4) ? (T)2.4e-7 : (T)4.5e-16;
-    const T R = (T)a.trad[t];
+    // staged radius: in a first pass over lists shared with the parent
+    // gradient/force tile, the margin over this tile's largest guessed
+    // support (formed as a list build forms it); else the tile's own radius
+    T R;
+    const bool shared = a.parent != nullptr && !a.fixup;
+    if (shared) {
+        const T hm = wave_max(act ? h : (T)0);
+        const float Rcf = 0.5f * (float)bi.L * (1.0f - 1e-6f);
+        float Rf = (float)(eps * hm * a.dmargin * (T)(1 + 4e-7));
+        if (!(Rf < Rcf)) {
+            if (a.dmargin == (T)1 && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
+            Rf = Rcf;
+        }
+        if (!(Rf > 0.f)) Rf = Rcf;
+        R = (T)Rf;
+    } else {
+        R = (T)a.trad[t];
+    }
+    const int lt = shared ? uniform(a.parent[t]) : t;  // whose list is staged
     const T hstage = R / eps;
     const T hedge = hstage * ((T)1 - (T)8 * tiny);  // largest h whose support is staged
     (void)L;
@@ -108,7 +126,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     };
     const T R2 = R * R;
     int flushes = 0;
-    int ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, R2, flushes, sweep);
+    int ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, R2, flushes, sweep);
     sweep(ns);
     const bool cached = flushes == 0;
     T Rc = R;  // radius of the staged set
@@ -177,7 +195,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
         }
         if (restage) {
             int fl = 0;
-            ns = stage_tile<L_DENS, T, CAP>(m, a, t, bi, g, Rs * Rs, fl, sweep);
+            ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, Rs * Rs, fl, sweep);
         }
         sweep(ns);
     }
@@ -432,7 +450,11 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     a.out = (T*)b.d_out;
     a.iout = b.d_int;
     if (bin.tile_d < bin.tile) {
-        launch_tasks_grouped<T>(bin, sc, s);  // one search per gradient/force tile
+        // one list per gradient/force tile, at the margin over its largest
+        // guessed support: its density tiles stage from it with their own
+        // radius (each gets exactly the list of its own search, in order)
+        launch_tasks<T>(bin, sc, 0, false, s);
+        a.parent = bin.dparent;
         if (sc.order == 0) launch_order(b, s);
     } else {
         launch_tasks<T>(b, sc, 0, false, s);

@@ -38,6 +38,8 @@ struct KArgs {
     const V4<T>* aux4;         // adjoint passes: per-particle staging data
     T* out;                    // sorted outputs, arrays of n
     T* gout;                   // joint gradient/force loop: the gradient outputs
+    const int32_t* parent;     // density first pass: each tile's list is its parent's (or null)
+    T dmargin;                 // density: staged radius over the largest guessed support
     int32_t* iout;             // sorted int outputs, arrays of n
     int64_t n;
     Counters* cnt;
@@ -209,20 +211,25 @@ __device__ __forceinline__ void gather_j(const KArgs<T>& a, int j, JData<LK, T>&
     if (Symmetric<LK>::value) r.h = a.hs[j];
 }
 
-// Stream tile t's candidate list through the lanes and stage it in LDS.
+// Stream the candidate list of tile lt (the tile's own, or for a density
+// tile in its first pass the list of the gradient/force tile containing it)
+// through the lanes and stage it in LDS.
 // Per batch of 64 candidates the entries (read one batch ahead) give the
 // j-particles, and every field the loop needs is gathered at once, so a
-// batch costs one memory round trip; the list was culled at build time, so
-// the cull here (radius R; for the symmetric loops also the j-particle's own
-// support) only matters when the caller passes a smaller R.  flush(nsurv) is
-// called whenever the buffer could overflow (the buffer is empty
-// afterwards).  Returns the number of staged survivors left for the caller.
+// batch costs one memory round trip.  The cull here (radius R from the
+// tile box; for the symmetric loops also the j-particle's own support)
+// keeps the candidates the tile needs: all of its own list unless the caller
+// passes a smaller R, a part of a parent's list.  flush(CAP) is called when
+// the buffer is full and more survivors arrive (the buffer is empty
+// afterwards), so a list and any longer list holding the same survivors in
+// the same order stage and flush identically.  Returns the number of staged
+// survivors left for the caller.
 template <int LK, typename T, int CAP, class WM, class Flush>
-__device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, const TileGeom& g,
+__device__ int stage_tile(WM& m, const KArgs<T>& a, int lt, const BoxInfo& bi, const TileGeom& g,
                           T R2, int& flushes, Flush&& flush) {
     const int lane = lane_id();
-    const int64_t off = uniform(a.cand_off[t]);
-    int64_t nc = uniform(a.cand_cnt[t]);
+    const int64_t off = uniform(a.cand_off[lt]);
+    int64_t nc = uniform(a.cand_cnt[lt]);
     if (off < 0) nc = 0;
     if (off + nc > a.cand_cap) nc = a.cand_cap > off ? a.cand_cap - off : 0;
     const T L = (T)bi.L;
@@ -237,11 +244,6 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
         JData<LK, T> r;
         if (have) gather_j<LK, T>(a, j, r);
         if (base + WAVE + lane < nc) e_next = a.cands[off + base + WAVE + lane];
-        if (nsurv + WAVE > CAP) {
-            flush(nsurv);
-            nsurv = 0;
-            ++flushes;
-        }
         bool pass = false;
         T xs = 0, ys = 0, zs = 0;
         if (have) {
@@ -261,37 +263,62 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int t, const BoxInfo& bi, co
             }
             pass = d2 < crit;
         }
-        const unsigned long long pm = ballot(pass);
+        // the staged record of this lane's candidate (the loop's layout)
+        V4<T> q0{}, q1{}, q2{}, q3{}, q4{};
         if (pass) {
-            const int k = nsurv + mbcnt(pm);
             const V4<T> pa = r.p, va = r.v;
             if (LK == L_DENS) {
-                m.s[0][k] = V4<T>{xs, ys, zs, pa.w};
-                m.s[1][k] = V4<T>{va.x, va.y, va.z, (T)0};
+                q0 = V4<T>{xs, ys, zs, pa.w};
+                q1 = V4<T>{va.x, va.y, va.z, (T)0};
             } else if (LK == L_FORCE) {
                 const V4<T> da = r.d;
                 const T Hj = mul_unfused(a.eps, r.h);
-                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                m.s[2][k] = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
-                m.s[3][k] = V4<T>{da.x, int_as<T>(j), va.w, pa.w / da.x};
+                q0 = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                q1 = V4<T>{va.x, va.y, va.z, da.z};
+                q2 = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
+                q3 = V4<T>{da.x, int_as<T>(j), va.w, pa.w / da.x};
             } else if (LK == L_ADJA) {
                 const V4<T> da = r.d;   // (rho, f, c, A)
                 const V4<T> wj = r.x;   // (dL/dax, dL/day, dL/daz, dL/ddu)
                 const T Hj = mul_unfused(a.eps, r.h);
-                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                m.s[1][k] = V4<T>{va.x, va.y, va.z, da.z};
-                m.s[2][k] = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
-                m.s[3][k] = V4<T>{da.x, wj.x, wj.y, wj.z};
-                m.s[4][k] = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
+                q0 = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                q1 = V4<T>{va.x, va.y, va.z, da.z};
+                q2 = V4<T>{pa.w, da.w, da.y, (T)1 / Hj};
+                q3 = V4<T>{da.x, wj.x, wj.y, wj.z};
+                q4 = V4<T>{wj.w, int_as<T>(j), (T)0, (T)0};
             } else {
                 // density adjoint: (m, rho_bar, rho'_bar, 1/H); implicit h: (lambda h^3, 1/H, idx, 0)
                 const T Hj = mul_unfused(a.eps, r.h);
-                m.s[0][k] = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
-                m.s[1][k] = r.x;
+                q0 = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                q1 = r.x;
             }
         }
-        nsurv += __popcll(pm);
+        auto put = [&](int k) {
+            constexpr int NV = LoopNV<LK>::NV;
+            m.s[0][k] = q0;
+            if (NV > 1) m.s[1][k] = q1;
+            if (NV > 2) m.s[2][k] = q2;
+            if (NV > 3) m.s[3][k] = q3;
+            if (NV > 4) m.s[4][k] = q4;
+        };
+        // survivors fill the buffer in list order; only when it is full and
+        // more arrive does it go to flush, so where flushes fall depends on
+        // the survivors alone, not on how the list is cut into batches
+        const unsigned long long pm = ballot(pass);
+        const int cnt = __popcll(pm);
+        const int rank = mbcnt(pm);
+        const int room = CAP - nsurv;
+        if (pass && rank < room) put(nsurv + rank);
+        if (cnt > room) {
+            wave_sync();
+            flush(CAP);
+            ++flushes;
+            wave_sync();
+            if (pass && rank >= room) put(rank - room);
+            nsurv = cnt - room;
+        } else {
+            nsurv += cnt;
+        }
         wave_sync();
     }
     return nsurv;
@@ -351,6 +378,8 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.aux4 = nullptr;
     a.out = nullptr;
     a.gout = nullptr;
+    a.parent = nullptr;
+    a.dmargin = (T)((sc.flags & SWSPH_FIXED_H) ? 1.0 : DENS_MARGIN);
     a.iout = nullptr;
     a.n = b.n;
     a.cnt = b.cnt;

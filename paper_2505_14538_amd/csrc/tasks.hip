@@ -351,171 +351,6 @@ void launch_order(const BinPtrs& b, hipStream_t s) {
                        b.order);
 }
 
-// Density lists built per group: the density tiles inside one gradient/
-// force tile (cells nest, so they are consecutive) share one cell search
-// over the group's box with the largest of their radii; each candidate is
-// then culled against every member's own box and radius, which gives each
-// member exactly the list its own search would give (in the group's search
-// order).  One wavefront per group runs the search twice: a counting pass
-// sizes the members' lists (allocated together from the bump counter), a
-// filling pass writes them.  The search is the costly part of a task build,
-// and groups are several times fewer than density tiles.
-struct GroupMem {
-    SearchMem sm;
-    int32_t lpre[LEAFCAP + 1];
-};
-
-template <typename T>
-__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks_group(TArgs<T> a, Tile* __restrict__ tiles_d,
-                                                                 const int32_t* __restrict__ dfirst) {
-    __shared__ GroupMem smem_group[TASK_WPB];
-    const int wave = threadIdx.x / WAVE;
-    GroupMem& m = smem_group[wave];
-    const int lane = lane_id();
-    const int64_t np = (int64_t)*a.ntiles;
-    unsigned long long listed = 0;  // flushed once per wavefront
-    for_each_item(a.heads, np, true, [&](int64_t p) {
-        const Tile tp = a.tiles[p];
-        const int d0 = uniform(dfirst[p]);
-        int nd = uniform(dfirst[p + 1]) - d0;
-        if (nd > WAVE) nd = WAVE;  // a group has at most 64 particles
-        if (nd <= 0) return;
-        const BoxInfo bi = a.boxtab[uniform(tp.box)];
-        const float L = (float)bi.L;
-        const float Rcap = 0.5f * L * (1.0f - 1e-6f);
-        // members: lane c < nd holds member c's box, radius and list offset
-        // (read by the other lanes with lane_val); radii from the largest h
-        // guess of each member
-        Tile tm;
-        float blo[3] = {0.f, 0.f, 0.f}, bhi[3] = {0.f, 0.f, 0.f};
-        if (lane < nd) {
-            tm = tiles_d[d0 + lane];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) { blo[d] = tm.lo[d]; bhi[d] = tm.hi[d]; }
-        }
-        float Rl = 0.f;
-        int moff = 0, gend = 0;
-        const int pc = uniform(tp.count);
-        const int pb = uniform(tp.begin);
-        const T h = lane < pc ? a.hs[pb + lane] : (T)0;
-        float Rmax = 0.f;
-        for (int c = 0; c < nd; ++c) {
-            const int cb = __shfl(lane < nd ? tm.begin : 0, c, WAVE);
-            const int cc = __shfl(lane < nd ? tm.count : 0, c, WAVE);
-            const int s = pb + lane;
-            const T hm = wave_max(lane < pc && s >= cb && s < cb + cc ? h : (T)0);
-            float R = (float)(a.eps * hm * a.margin * (T)(1 + 4e-7));
-            if (!(R < Rcap)) {
-                if (a.margin == (T)1 && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
-                R = Rcap;
-            }
-            if (!(R > 0.f)) R = Rcap;
-            if (lane == 0) a.trad[d0 + c] = R;
-            if (lane == c) Rl = R;
-            Rmax = fmaxf(Rmax, R);
-        }
-        // member c's squared radius, in lane c, formed as the loops form it
-        T R2c = (T)0;
-        if (lane < nd) {
-            const T Rt = (T)Rl;
-            R2c = Rt * Rt;
-        }
-        TileGeom g;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) { g.lo[d] = tp.lo[d]; g.hi[d] = tp.hi[d]; }
-        const T Lt = (T)bi.L;
-        const float R2p = Rmax * Rmax;
-        for (int pass = 0; pass < 2; ++pass) {
-            SearchState st;
-            search_init(m.sm, st, bi, g, Rmax);
-            int run = 0;  // lane c < nd: entries of member c so far
-            for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
-                const bool done = search_step<false>(m.sm, st, bi, g, R2p, a.cstart, a.hpyr,
-                                                     a.leaf_max, a.cnt);
-                if (st.nleaf > 0) {
-                    int c0 = lane < st.nleaf ? m.sm.lcnt[lane] : 0;
-                    int c1 = lane + WAVE < st.nleaf ? m.sm.lcnt[lane + WAVE] : 0;
-                    int tot0 = 0, tot1 = 0;
-                    const int e0 = wave_excl_scan(c0, tot0);
-                    const int e1 = wave_excl_scan(c1, tot1);
-                    m.lpre[lane] = e0;
-                    m.lpre[lane + WAVE] = tot0 + e1;
-                    if (lane == 0) m.lpre[2 * WAVE] = tot0 + tot1;
-                    wave_sync();
-                    const int nl = st.nleaf;
-                    const int nv = tot0 + tot1;
-                    for_candidates<T, false>(
-                        m.sm, m.lpre, nl, nv, a.pos4, a.hs, a.n,
-                        [&](bool have, int j, int code, const V4<T>& pa, T) {
-                        T xs = 0, ys = 0, zs = 0;
-                        uint32_t ent = 0;
-                        if (have) {
-                            int sx, sy, sz;
-                            shift_of(code, sx, sy, sz);
-                            xs = pa.x + (T)sx * Lt;
-                            ys = pa.y + (T)sy * Lt;
-                            zs = pa.z + (T)sz * Lt;
-                            ent = (uint32_t)j | ((uint32_t)code << 26);
-                        }
-                        // member c's test (its box and radius read from lane c)
-                        auto inside = [&](int c) {
-                            const T r2c = lane_val(R2c, c);
-                            const T lx = (T)lane_val(blo[0], c), hx = (T)lane_val(bhi[0], c);
-                            const T ly = (T)lane_val(blo[1], c), hy = (T)lane_val(bhi[1], c);
-                            const T lz = (T)lane_val(blo[2], c), hz = (T)lane_val(bhi[2], c);
-                            const T gx = max((T)0, max(lx - xs, xs - hx));
-                            const T gy = max((T)0, max(ly - ys, ys - hy));
-                            const T gz = max((T)0, max(lz - zs, zs - hz));
-                            return have && dist2_unfused(gx, gy, gz) < r2c;
-                        };
-                        if (pass == 0) {
-                            // counting pass: sizes only
-                            for (int c = 0; c < nd; ++c) {
-                                const unsigned long long pm = ballot(inside(c));
-                                if (lane == c) run += __popcll(pm);
-                            }
-                        } else {
-                            // filling pass (gend: end of the group's space)
-                            for (int c = 0; c < nd; ++c) {
-                                const bool pass_c = inside(c);
-                                const unsigned long long pm = ballot(pass_c);
-                                const int at = lane_val(moff, c) + lane_val(run, c) + mbcnt(pm);
-                                if (pass_c && at < gend) a.cands[at] = ent;
-                                if (lane == c) run += __popcll(pm);
-                            }
-                        }
-                    });
-                    st.nleaf = 0;
-                    wave_sync();
-                }
-                if (done) break;
-            }
-            if (pass == 0) {
-                // sizes -> one allocation for the group, offsets per member
-                int tot = 0;
-                const int e = wave_excl_scan(lane < nd ? run : 0, tot);
-                int64_t base = 0;
-                if (lane == 0) base = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)tot);
-                listed += (unsigned long long)tot;
-                base = __shfl(base, 0, WAVE);
-                const bool fits = base + tot <= a.cand_cap;
-                if (!fits && lane == 0) latch(a.cnt, SWSPH_ST_CAPACITY);
-                gend = (int)(base + tot);
-                if (lane < nd) {
-                    moff = (int32_t)(base + e);
-                    a.cand_off[d0 + lane] = fits ? (int32_t)(base + e) : -1;
-                    a.cand_cnt[d0 + lane] = fits ? run : 0;
-                    tiles_d[d0 + lane].cost = (float)tm.count * (float)run;
-                }
-                wave_sync();
-                if (!fits) break;
-            }
-        }
-        wave_sync();
-    });
-    if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
-}
-
 template <typename T>
 static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin);
 
@@ -538,20 +373,6 @@ static unsigned resident_grid(const void* kern, int threads) {
             break;
         }
     return g;
-}
-
-// The first density task build with grouped searches (density tiles smaller
-// than the gradient/force tiles).
-template <typename T>
-void launch_tasks_grouped(const BinPtrs& bin, const Scheme& sc, hipStream_t s) {
-    if (bin.n <= 0) return;
-    const double margin = (sc.flags & SWSPH_FIXED_H) ? 1.0 : 1.25;
-    TArgs<T> a = targs<T>(bin, sc, margin);
-    launch_fill_u32(&bin.cnt->cand_used, 2, 0u, s);
-    launch_fill_u32(a.heads, 2 * NSEG, 0u, s);
-    hipLaunchKernelGGL(k_tasks_group<T>,
-                       dim3(resident_grid((const void*)k_tasks_group<T>, TASK_WPB * WAVE)),
-                       dim3(TASK_WPB * WAVE), 0, s, a, bin.tiles_d, (const int32_t*)bin.dfirst);
 }
 
 template <typename T>
@@ -584,7 +405,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s) {
     if (b.n <= 0) return;
-    const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? 1.25 : 1.0;
+    const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? DENS_MARGIN : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
     if (fixup) {
         // the flagged density tiles, compacted by k_fix_list
@@ -600,8 +421,6 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
                        (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
-template void launch_tasks_grouped<float>(const BinPtrs&, const Scheme&, hipStream_t);
-template void launch_tasks_grouped<double>(const BinPtrs&, const Scheme&, hipStream_t);
 template void launch_tasks<float>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
 template void launch_tasks<double>(const BinPtrs&, const Scheme&, int, bool, hipStream_t);
 
