@@ -168,7 +168,8 @@ typedef struct swsph_input_grad {
 typedef struct swsph_stats {
     uint32_t status;             /* SWSPH_ST_* bits latched since the last bin */
     uint32_t n_tiles;            /* gradient/force tile tasks of the last bin */
-    uint64_t pairs_tested[4];    /* candidate pairs tested: density sweep, gradient, force, backward */
+    uint64_t pairs_tested[4];    /* candidate pairs tested: density (all sweeps), gradient, force
+                                    (the joint kernel: the same tests), backward */
     uint64_t pairs_inside[4];    /* pairs inside the support (useful pairs) */
     uint64_t newton_sweeps;      /* sum over density tiles of their sweeps */
     uint32_t newton_max;         /* largest sweep count of a tile */
@@ -204,9 +205,10 @@ int swsph_workspace_bytes(const swsph_plan* plan, int64_t n, int32_t n_box,
 
 /* Bin the particles: per-box Morton key on a 2^k grid of cubic cells, a
  * device counting sort on that key (stable: equal keys keep input order),
- * sorted copies of the particle data in the workspace, the cell table, the
- * i-tiles and the density task list.  Section 2.2 (cells, self and pair
- * tasks).  Clears the device status word. */
+ * sorted copies of the particle data in the workspace, the cell table and
+ * the i-tiles (cells of at most tile / tile_dens particles).  Section 2.2
+ * (cells, self and pair tasks).  The task lists are built by the loop calls.
+ * Clears the device status word. */
 int swsph_bin(swsph_plan* plan, const swsph_particles* p, void* ws, void* stream);
 
 /* Density loop with Newton iteration on h (Sec. 2.1.2; SWSPH_FIXED_H: at

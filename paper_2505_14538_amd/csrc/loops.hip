@@ -1,15 +1,18 @@
-// loops.hip -- gfx950 kernels of the density, gradient and force loops.
+// loops.hip -- gfx950 kernels of the density loop and of the joint gradient
+// and force loop.
 //
 // Work decomposition (MI355X-first; the paper's CUDA kernels are not shown
 // and were written for V100/H100/L40, so nothing is carried over):
-//   * task = one i-tile of up to `tile` consecutive binned particles (one
-//     particle per lane of a 64-wide wavefront);
-//   * the tile's task list (its own and neighbouring cells, i.e. the paper's
-//     self and pair tasks, Sec. 2.2.2) comes from tasks.hip as a CSR of
-//     particle ranges with periodic-image codes;
-//   * the j-particles of those ranges are streamed through the lanes
-//     (coalesced loads), culled against the tile's bounding box by squared
-//     distance, and the survivors are staged in LDS (arrays of 4-vectors);
+//   * task = one i-tile: a cell of the cell tree holding at most `tile`
+//     binned particles (lanes map to i-slots x streams of a 64-wide
+//     wavefront);
+//   * the tile's task list (the particles of its own and neighbouring cells,
+//     i.e. the paper's self and pair tasks, Sec. 2.2.2) comes from tasks.hip
+//     as candidate entries (particle index and periodic-image code), already
+//     culled against the tile box;
+//   * the candidates are streamed through the lanes (coalesced entry reads,
+//     one gather round trip per batch), culled by the loop's own radius and
+//     staged in LDS (arrays of 4-vectors);
 //   * every lane then runs over the staged j-particles (LDS broadcast reads)
 //     and accumulates its own sums -- a gather, so no atomics and a fixed
 //     summation order (results are bitwise reproducible);

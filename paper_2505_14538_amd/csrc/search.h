@@ -10,7 +10,8 @@
 // symmetric force loop, below the cell's own largest support radius), and
 // splits a kept cell into its 8 children while it holds more than `leaf_max`
 // particles and is not entirely within reach.  Kept cells that are not split
-// are the tile's task list ("leaves": one contiguous particle range each).
+// ("leaves": one contiguous particle range each, with a periodic-image code)
+// are handed out in batches; tasks.hip walks their particles.
 //
 // Every loop is bounded: the search processes at most SEARCH_MAX_CHUNKS
 // chunks per call and latches SWSPH_ST_LOOPCAP if it had to stop early.
@@ -219,17 +220,6 @@ __device__ __forceinline__ int wave_excl_scan(int v, int& total) {
     x += (row > 0 ? r0 : 0) + (row > 1 ? r1 : 0) + (row > 2 ? r2 : 0);
     total = r0 + r1 + r2 + r3;
     return x - v;
-}
-
-// A leaf in the task list: particle range [beg, beg + count) of one cell,
-// shifted by a periodic image (code in the top 5 bits of the second word).
-__device__ __forceinline__ int2 pack_leaf(int32_t beg, int32_t num, int shift) {
-    return make_int2(beg, (int32_t)(((uint32_t)shift << 26) | ((uint32_t)num & 0x3ffffffu)));
-}
-__device__ __forceinline__ void unpack_leaf(int2 v, int32_t& beg, int32_t& num, int& shift) {
-    beg = v.x;
-    num = (int32_t)((uint32_t)v.y & 0x3ffffffu);
-    shift = (int)((uint32_t)v.y >> 26);
 }
 
 }  // namespace swsph

@@ -72,7 +72,7 @@ struct Layout {
     uint64_t fine_count, cstart, scan_part;
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
     uint64_t tiles, order, tiles_d, order_d, dparent, ord_table, ord_base;
-    // task lists (CSR of cells per tile) and density fix-up state
+    // task lists (candidate entries per tile) and density fix-up state
     uint64_t cand_cnt, cand_off, cands, trad, tflag;
     // sorted-order results
     uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
