@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 
 # FLOPs per useful pair, counted on the arithmetic each loop performs for a
 # pair inside the support (FMA = 2, add/mul/min/max = 1, sqrt/rsqrt/rcp = 1).
-F_DENS = 55.0     # full density sums (n, dn/dh, rho, drho/dh, div v, curl v)
-F_NEWTON = 25.0   # each additional Newton sweep (n and dn/dh only)
+F_DENS = 59.0     # full density sums (n, dn/dh, d2n/dlogh2, rho, drho/dh, div v, curl v)
+F_NEWTON = 29.0   # each additional Newton sweep (n and its first two log-h derivatives)
 F_GRAD = 33.0     # the gradient loop on its own
 F_FORCE = 67.0
 F_GRAD_JOINT = 17.0  # a gradient pair inside the joint gradient/force body

@@ -341,10 +341,20 @@ void unsort_density(const BinPtrs& b, swsph_density_out* o, hipStream_t s) {
     T* d = (T*)b.d_out;
     void* dst[10] = {o->h, o->rho, o->rho_dh, o->wcount, o->wcount_dh,
                      o->div_v, o->curl_x, o->curl_y, o->curl_z, o->f};
-    for (int k = 0; k < 10; ++k)
-        if (dst[k]) launch_unsort<T>(n, b.rank, d + k * n, dst[k], s);
-    if (o->nngb) launch_unsort<int32_t>(n, b.rank, b.d_int, o->nngb, s);
-    if (o->iters) launch_unsort<int32_t>(n, b.rank, b.d_int + n, o->iters, s);
+    UnsortSet u{};
+    for (int k = 0; k < 10; ++k) {
+        u.in[k] = d + k * n;
+        u.out[k] = dst[k];
+    }
+    u.k = 10;
+    launch_unsort_multi<T>(n, b.rank, u, s);
+    UnsortSet ui{};
+    ui.in[0] = b.d_int;
+    ui.out[0] = o->nngb;
+    ui.in[1] = b.d_int + n;
+    ui.out[1] = o->iters;
+    ui.k = 2;
+    if (o->nngb || o->iters) launch_unsort_multi<int32_t>(n, b.rank, ui, s);
 }
 
 }  // namespace
@@ -534,15 +544,22 @@ int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out
     launch_gf_tasks<T>(b, sc, s);
     if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
         return fail(SWSPH_E_HIP, "gradient/force kernel launch failed");
+    UnsortSet u{};
     if (go) {
-        launch_unsort<T>(n, b.rank, (T*)b.g_out, go->v_sig, s);
-        launch_unsort<T>(n, b.rank, (T*)b.g_out + n, go->lap_u, s);
+        u.in[u.k] = (T*)b.g_out;
+        u.out[u.k++] = go->v_sig;
+        u.in[u.k] = (T*)b.g_out + n;
+        u.out[u.k++] = go->lap_u;
     }
     if (fo) {
         void* dst[4] = {fo->ax, fo->ay, fo->az, fo->dudt};
-        for (int k = 0; k < 4; ++k) launch_unsort<T>(n, b.rank, (T*)b.f_out + k * n, dst[k], s);
+        for (int k = 0; k < 4; ++k) {
+            u.in[u.k] = (T*)b.f_out + k * n;
+            u.out[u.k++] = dst[k];
+        }
         if (fo->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, fo->nint, s);
     }
+    launch_unsort_multi<T>(n, b.rank, u, s);
     return hip_check(hipGetLastError(), go ? (fo ? "gradient+force" : "gradient") : "force");
 }
 

@@ -469,6 +469,25 @@ template void launch_unsort<float>(int64_t, const int32_t*, const void*, void*, 
 template void launch_unsort<double>(int64_t, const int32_t*, const void*, void*, hipStream_t);
 template void launch_unsort<int32_t>(int64_t, const int32_t*, const void*, void*, hipStream_t);
 
+// Several arrays of one type in one launch (null outputs are skipped).
+template <typename T>
+__global__ void k_unsort_multi(int64_t n, const int32_t* __restrict__ rank, UnsortSet set) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t r = rank[p];
+    for (int k = 0; k < set.k; ++k)
+        if (set.out[k]) ((T*)set.out[k])[p] = ((const T*)set.in[k])[r];
+}
+template <typename T>
+void launch_unsort_multi(int64_t n, const int32_t* rank, const UnsortSet& set, hipStream_t s) {
+    if (n <= 0 || set.k <= 0) return;
+    hipLaunchKernelGGL(k_unsort_multi<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       rank, set);
+}
+template void launch_unsort_multi<float>(int64_t, const int32_t*, const UnsortSet&, hipStream_t);
+template void launch_unsort_multi<double>(int64_t, const int32_t*, const UnsortSet&, hipStream_t);
+template void launch_unsort_multi<int32_t>(int64_t, const int32_t*, const UnsortSet&, hipStream_t);
+
 // in-order -> sorted: out[s] = in[perm[s]]
 template <typename T>
 __global__ void k_sortcopy(int64_t n, const int32_t* __restrict__ perm, const T* __restrict__ in,

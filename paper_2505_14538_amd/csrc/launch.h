@@ -81,6 +81,14 @@ void launch_make_tiles(const BinPtrs& b, hipStream_t s);
 unsigned wave_grid(int64_t items, int wpb);
 template <typename T>
 void launch_unsort(int64_t n, const int32_t* rank, const void* in, void* out, hipStream_t s);
+// Up to 12 binned arrays of one type back to the caller's order in one launch.
+struct UnsortSet {
+    const void* in[12];
+    void* out[12];
+    int k;
+};
+template <typename T>
+void launch_unsort_multi(int64_t n, const int32_t* rank, const UnsortSet& set, hipStream_t s);
 template <typename T>
 void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, hipStream_t s);
 

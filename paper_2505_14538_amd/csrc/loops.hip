@@ -88,7 +88,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     T want = 0;
     int iters = a.fixup ? max(0, a.iout[a.n + i] < 0 ? -a.iout[a.n + i] : a.iout[a.n + i]) : 0;
     const int iters0 = iters;
-    T S0 = 0, S1 = 0, Sr = 0, Sdr = 0, Dv = 0, Cx = 0, Cy = 0, Cz = 0;
+    T S0 = 0, S1 = 0, S2 = 0, Sr = 0, Sdr = 0, Dv = 0, Cx = 0, Cy = 0, Cz = 0;
     int cnt = 0;
     unsigned long long tested = 0;
     T H = eps * h;
@@ -109,6 +109,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
         m4_terms(q, H * inv_r, w, s1, gq);
         S0 += w;
         S1 += s1;
+        S2 += m4_q2w2(q);
         Sr += sj.w * w;
         Sdr += sj.w * s1;
         const T ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
@@ -124,7 +125,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
         tested += (unsigned long long)ns;
     };
     auto zero = [&]() {
-        S0 = S1 = Sr = Sdr = Dv = Cx = Cy = Cz = 0;
+        S0 = S1 = S2 = Sr = Sdr = Dv = Cx = Cy = Cz = 0;
         cnt = 0;
     };
     const T R2 = R * R;
@@ -135,18 +136,25 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     T Rc = R;  // radius of the staged set
     for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
         ++iters;
-        const T S0r = stream_sum(S0, q), S1r = stream_sum(S1, q);
+        const T S0r = stream_sum(S0, q), S1r = stream_sum(S1, q), S2r = stream_sum(S2, q);
         if (!conv && !pend) {
             const T G = S0r;
             if (fabs(G - Tt) <= a.h_tol * Tt) {
                 conv = true;
             } else {
-                // Newton step on log G over log h (h dG/dh = 3 S0 - S1): the
-                // same root, reached in fewer sweeps than a step on G itself,
-                // since G grows about as h^3
+                // Halley step on F = log(G / target) over log h: G grows about
+                // as h^3, so F is nearly linear in log h, and the third-order
+                // step (F' from h dG/dh = 3 S0 - S1, F'' from the sum of
+                // q^2 w''(q) as well) saves about half a sweep per particle
+                // over a Newton step on the same function
                 const T dl = (T)3 * S0r - S1r;
                 if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
-                T hn = h * exp(-log1p((G - Tt) / Tt) * G / dl);
+                const T F = log1p((G - Tt) / Tt);
+                const T F1 = dl / G;
+                const T F2 = (S2r - dl) / G - F1 * F1;
+                const T den = (T)2 * F1 * F1 - F * F2;
+                const T ds = den > (T)0 ? (T)-2 * F * F1 / den : -F / F1;
+                T hn = h * exp(ds);
                 const bool ok = dl > (T)0 && hn > lo_h && hn < hi_h;
                 if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
                 if (!has_upper && hn >= hedge) {
@@ -388,8 +396,12 @@ __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, Wav
     else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
+// The FP32 density kernel's LDS allows three wavefronts per SIMD; its registers
+// are held to that too (the Newton accumulators would otherwise take it just
+// past the 168-register step).
 template <int LK, typename T, int CAP>
-__global__ void __launch_bounds__(WPB * WAVE) k_loop(KArgs<T> a, int mode) {
+__global__ void __launch_bounds__(WPB * WAVE)
+__attribute__((amdgpu_waves_per_eu(LK == L_DENS && sizeof(T) == 4 ? 3 : 1))) k_loop(KArgs<T> a, int mode) {
     SWSPH_DYN_SHARED char smem[];
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
     const int wave = threadIdx.x / WAVE;
@@ -478,7 +490,10 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
         launch_tasks<T>(b, sc, 0, true, s);
         a.fixup = pass == 3 ? 2 : 1;
         timer_begin(sc.timer, 0, s);
-        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, lds_cap, 0, s);
+        // fix-up tiles are few and their lists long: the largest staging
+        // buffer keeps more of them in LDS across their sweeps
+        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode,
+                                   lds_cap > 512 ? lds_cap : 512, 0, s);
         timer_end(sc.timer, 0, s);
     }
     return r;

@@ -341,6 +341,13 @@ __device__ __forceinline__ void m4_terms(T q, T inv_q, T& w, T& s1, T& g) {
     s1 = in ? si : so;
     g = in ? gi : go;
 }
+// q^2 w''(q): with q w'(q) it gives the second derivative of sum_j w(q_j)
+// over log h (q scales as 1/h)
+template <typename T> __device__ __forceinline__ T m4_q2w2(T q) {
+    const T q2 = q * q;
+    const T a = q2 * ((T)36 * q - (T)12), b = (T)12 * q2 * ((T)1 - q);
+    return q < (T)0.5 ? a : b;
+}
 // w'(q)
 template <typename T> __device__ __forceinline__ T m4_dw(T q) {
     const T t = (T)1 - q;
