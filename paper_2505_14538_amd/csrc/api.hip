@@ -54,10 +54,13 @@ constexpr int KMAX = 10;               // Morton key: 3 x 10 bits per box
 constexpr int64_t FINE_MAX = int64_t(1) << 29;
 
 // Candidate-list capacity: 160 entries per particle (lists of cell tiles
-// hold ~30-80 per particle on the clustered and uniform sets), below 2^31
-// (int32 offsets).  Overflow latches SWSPH_ST_CAPACITY.
+// hold ~30-80 per particle on the clustered and uniform sets) plus one
+// build window per wavefront that can take one (at most one per tile), below
+// 2^31 (int32 offsets).  Overflow latches SWSPH_ST_CAPACITY.
 int64_t cand_capacity(int64_t n) {
-    return std::min<int64_t>(160 * n + 65536, (int64_t(1) << 31) - 1);
+    const int64_t waves = std::min<int64_t>(std::max<int64_t>(n, 1),
+                                            (int64_t)device_cu_count() * BUILD_WAVES_PER_CU);
+    return std::min<int64_t>(160 * n + 65536 + waves * TASK_CHUNK, (int64_t(1) << 31) - 1);
 }
 
 int choose_k(int64_t nb) {

@@ -79,6 +79,11 @@ void launch_gather(const swsph_particles* p, const BoxInfo* boxtab, const uint32
 template <typename T>
 void launch_make_tiles(const BinPtrs& b, hipStream_t s);
 unsigned wave_grid(int64_t items, int wpb);
+// Task-list entries a build wavefront takes from the bump counter at a time
+// (its window); the candidate capacity leaves room for one window per
+// wavefront that can be resident (32 per CU).
+constexpr int64_t TASK_CHUNK = 8192;
+constexpr int64_t BUILD_WAVES_PER_CU = 32;
 template <typename T>
 void launch_unsort(int64_t n, const int32_t* rank, const void* in, void* out, hipStream_t s);
 // Up to 12 binned arrays of one type back to the caller's order in one launch.

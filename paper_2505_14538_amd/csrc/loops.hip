@@ -401,7 +401,7 @@ __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, Wav
 // past the 168-register step).
 template <int LK, typename T, int CAP>
 __global__ void __launch_bounds__(WPB * WAVE)
-__attribute__((amdgpu_waves_per_eu(LK == L_DENS && sizeof(T) == 4 ? 3 : 1))) k_loop(KArgs<T> a, int mode) {
+SWSPH_WAVES_PER_EU(LK == L_DENS && sizeof(T) == 4 ? 3 : 1) k_loop(KArgs<T> a, int mode) {
     SWSPH_DYN_SHARED char smem[];
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
     const int wave = threadIdx.x / WAVE;

@@ -7,6 +7,11 @@
 
 #include "swsph.h"
 
+// Occupancy target of a kernel (wavefronts per SIMD the register
+// allocation must allow).
+#ifndef SWSPH_WAVES_PER_EU
+#define SWSPH_WAVES_PER_EU(n) __attribute__((amdgpu_waves_per_eu(n)))
+#endif
 // Dynamic LDS of a kernel.
 #ifndef SWSPH_DYN_SHARED
 #define SWSPH_DYN_SHARED extern __shared__ __align__(16)

@@ -6,6 +6,8 @@
 // do not depend on the placement).  The build also fixes the tile's search
 // radius (trad), which the loop kernels reuse, and a cost estimate (tile
 // particles x candidates) for task ordering.
+#include <algorithm>
+
 #include "launch.h"
 #include "search.h"
 
@@ -43,20 +45,25 @@ struct TArgs {
 // below the loop's radius R (force: below max(R, H_j), the symmetric
 // support) -- as entries j | image << 26 (periodic image code, see
 // search.h).  The cull is done once here, so the loops only gather.
-// The entries collect in LDS (up to TASK_BUF) and are copied to space taken
-// from a device bump counter, so each list is contiguous; a longer list is
-// counted, given exactly that much space, and the search runs again writing
-// straight to global memory.  The tile's radius and cost (particles x
-// candidates) are recorded.  Wavefront-uniform.
-#ifndef SWSPH_TASK_BUF
-#define SWSPH_TASK_BUF 2048
-#endif
-constexpr int TASK_BUF = SWSPH_TASK_BUF;  // entries buffered in LDS per wavefront
+// Each wavefront owns a window of the candidate array, TASK_CHUNK entries
+// taken from a device bump counter, and writes its tiles' lists into it one
+// after another, straight to their final place (no staging buffer, no copy):
+// a tile starts with at least TASK_BUF free entries in the window, and a
+// list that turns out longer is counted, given exactly that much space from
+// the same counter, and the search runs again writing there.  Lists stay
+// contiguous; the window's unused tail is left as a gap.  The tile's radius
+// and cost (particles x candidates) are recorded.  Wavefront-uniform.
+constexpr int TASK_BUF = 2048;     // longest list written in one search
+static_assert(TASK_CHUNK >= TASK_BUF, "a window must hold the longest single-search list");
 
 struct TaskMem {
     SearchMem sm;
     int32_t lpre[LEAFCAP + 1];  // prefix sums of the particle counts of a leaf batch
-    uint32_t buf[TASK_BUF];
+};
+
+// The wavefront's window [at, end) of the candidate array.
+struct TaskWindow {
+    int64_t at = 0, end = 0;
 };
 
 // The particles of a batch of leaves (cell ranges with image codes, their
@@ -119,8 +126,21 @@ __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_
 
 // Returns the number of entries listed for the tile (uniform over the wave).
 template <typename T, int MODE>
-__device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64_t t, int fixup) {
+__device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, const Tile& tl,
+                            int64_t t, int fixup) {
     const int lane = lane_id();
+    if (win.end - win.at < TASK_BUF) {
+        // a new window; none left -> the capacity error below
+        int64_t w = 0;
+        if (lane == 0) {
+            w = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)TASK_CHUNK);
+            if (w + TASK_CHUNK > a.cand_cap) w = -1;
+        }
+        w = __shfl(w, 0, WAVE);
+        win.at = w;
+        win.end = w < 0 ? w : w + TASK_CHUNK;
+    }
+    const bool room = win.at >= 0;
     const BoxInfo bi = a.boxtab[tl.box];
     const float L = (float)bi.L;
     const float Rcap = 0.5f * L * (1.0f - 1e-6f);
@@ -199,8 +219,8 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64
                             const int64_t at = total + mbcnt(pm);
                             if (direct) {
                                 if (at < known) a.cands[base + at] = ent;
-                            } else if (at < TASK_BUF) {
-                                m.buf[at] = ent;
+                            } else if (room && at < TASK_BUF) {
+                                a.cands[win.at + at] = ent;
                             }
                         }
                         total += __popcll(pm);
@@ -211,26 +231,31 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64
             if (done) break;
         }
         if (direct) break;
-        // first round: record, allocate, copy (or go round again)
+        // first round: a list that fit is in place in the window; a longer
+        // one gets exact space (or the capacity error) and a second round
         int64_t at = 0;
         listed = total;
+        const bool inwin = room && total <= TASK_BUF;
         if (lane == 0) {
             a.tiles[t].cost = (float)tl.count * (float)total;
-            at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
-            const bool fits = at + total <= a.cand_cap;
-            a.cand_off[t] = fits ? (int32_t)at : -1;
-            a.cand_cnt[t] = fits ? (int32_t)total : 0;
-            if (!fits) {
-                latch(a.cnt, SWSPH_ST_CAPACITY);
+            if (inwin) {
+                at = win.at;
+            } else if (room) {
+                at = (int64_t)atomicAdd(&a.cnt->cand_used, (unsigned long long)total);
+                if (at + total > a.cand_cap) at = -1;
+            } else {
                 at = -1;
             }
+            a.cand_off[t] = at >= 0 ? (int32_t)at : -1;
+            a.cand_cnt[t] = at >= 0 ? (int32_t)total : 0;
+            if (at < 0) latch(a.cnt, SWSPH_ST_CAPACITY);
         }
         at = __shfl(at, 0, WAVE);
-        if (at < 0) break;
-        if (total <= TASK_BUF) {
-            for (int k = lane; k < total; k += WAVE) a.cands[at + k] = m.buf[k];
+        if (inwin) {
+            win.at += total;
             break;
         }
+        if (at < 0) break;
         direct = true;
         base = at;
         known = total;
@@ -244,13 +269,15 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, const Tile& tl, int64
 // 2 force (eps*hmax, and cells whose own support reaches the tile).
 // One wavefront per tile; tiles are popped from the item queue (for_each_item).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup) {
+__global__ void __launch_bounds__(TASK_WPB * WAVE)
+SWSPH_WAVES_PER_EU(sizeof(T) == 4 ? 5 : 1) k_tasks(TArgs<T> a, int fixup) {
     __shared__ TaskMem smem_task[TASK_WPB];
     const int wave = threadIdx.x / WAVE;
     TaskMem& m = smem_task[wave];
     const int lane = lane_id();
     const int64_t nt = (int64_t)*a.ntiles;
     unsigned long long listed = 0;  // flushed once per wavefront
+    TaskWindow win;
     for_each_item(a.heads, nt, a.list == nullptr, [&](int64_t k) {
         const int64_t t = a.list ? (int64_t)uniform(a.list[k]) : k;
         Tile tl = a.tiles[t];
@@ -264,7 +291,7 @@ __global__ void __launch_bounds__(TASK_WPB * WAVE) k_tasks(TArgs<T> a, int fixup
             }
             return;
         }
-        listed += (unsigned long long)task_one<T, MODE>(a, m, tl, t, fixup);
+        listed += (unsigned long long)task_one<T, MODE>(a, m, win, tl, t, fixup);
     });
     if (lane == 0 && listed) atomicAdd(&a.cnt->listed, listed);
 }
@@ -417,7 +444,11 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
     launch_fill_u32(&b.cnt->cand_used, 2, 0u, s);
     launch_fill_u32(a.heads, 2 * NSEG, 0u, s);
-    hipLaunchKernelGGL(kern, dim3(resident_grid((const void*)kern, TASK_WPB * WAVE)), block, 0, s, a,
+    // at most BUILD_WAVES_PER_CU wavefronts per CU take windows (the
+    // candidate capacity counts on it)
+    const unsigned gmax = (unsigned)(device_cu_count() * (BUILD_WAVES_PER_CU / TASK_WPB));
+    const unsigned grid = std::min(resident_grid((const void*)kern, TASK_WPB * WAVE), gmax);
+    hipLaunchKernelGGL(kern, dim3(grid), block, 0, s, a,
                        (int)fixup);
     if (!fixup && sc.order == 0) launch_order(b, s);
 }
