@@ -396,12 +396,13 @@ __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, Wav
     else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
-// The FP32 density kernel's LDS allows three wavefronts per SIMD; its registers
-// are held to that too (the Newton accumulators would otherwise take it just
-// past the 168-register step).
+// Register budgets matching what LDS allows (FP32): three wavefronts per
+// SIMD for the density kernel (its Newton accumulators would otherwise take
+// it just past the 168-register step), four for the gradient/force kernel.
 template <int LK, typename T, int CAP>
 __global__ void __launch_bounds__(WPB * WAVE)
-SWSPH_WAVES_PER_EU(LK == L_DENS && sizeof(T) == 4 ? 3 : 1) k_loop(KArgs<T> a, int mode) {
+SWSPH_WAVES_PER_EU(sizeof(T) != 4 ? 1 : (LK == L_DENS ? 3 : (LK == L_FORCE ? 4 : 1)))
+k_loop(KArgs<T> a, int mode) {
     SWSPH_DYN_SHARED char smem[];
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
     const int wave = threadIdx.x / WAVE;

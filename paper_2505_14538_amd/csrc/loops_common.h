@@ -13,8 +13,12 @@ constexpr int LC = 32;  // entries of a lane's hit list
 
 template <typename T, int CAP, int NV>
 struct WaveMem {
+    // hit-list length: 16 for the loops staging four or more 4-vectors per
+    // particle, so the gradient/force kernel's 128 staged particles and
+    // lists take 10 KB per wavefront and four wavefronts per SIMD fit LDS
+    static constexpr int HL = NV >= 4 ? 16 : LC;
     V4<T> s[NV][CAP];          // staged j-particles
-    uint16_t lst[LC][WAVE];    // per-lane hit lists (staged indices), column per lane
+    uint16_t lst[HL][WAVE];    // per-lane hit lists (staged indices), column per lane
 };
 
 template <typename T>
@@ -99,7 +103,7 @@ template <typename V> __device__ __forceinline__ V stream_max(V v, const LaneMap
 // thus runs with nearly all lanes busy instead of under the divergence of
 // the test (only a few of the tested pairs lie inside the support), and
 // each lane still accumulates its pairs in staged order, so results do not
-// depend on LC.  Tests go PL_U at a time (their LDS reads issue together),
+// depend on the list length.  Tests go PL_U at a time (their LDS reads issue together),
 // the body two at a time (the second pair's reads overlap the first's
 // arithmetic); loop control is wavefront-uniform.  test(k, ok) must return
 // false when !ok (k is then a valid but repeated index).
@@ -136,7 +140,7 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
                 ++c;
             }
         }
-        if (ballot(c > LC - PL_U) != 0ull) drain();
+        if (ballot(c > WM::HL - PL_U) != 0ull) drain();
     }
     drain();
 }
