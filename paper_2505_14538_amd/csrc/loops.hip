@@ -252,7 +252,7 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     const unsigned long long ins = (unsigned long long)wave_sum(lead ? cnt : 0);
     if (lane == 0) {
         if (pmask) {
-            T Rn = eps * wmax * (T)1.125;
+            T Rn = eps * wmax * (T)1.0625;
             if (!(Rn < Rcap)) Rn = Rcap;
             a.trad[t] = (float)Rn;
             a.tflag[t] = 1;
