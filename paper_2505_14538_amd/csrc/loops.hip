@@ -22,6 +22,8 @@
 // Launch modes: a persistent kernel whose wavefronts pull tasks from a device
 // queue, a flat launch (one wavefront per task) and one launch per task (the
 // per-task offload baseline).  Every loop has a fixed upper bound.
+#include <algorithm>
+
 #include "loops_common.h"
 
 namespace swsph {
@@ -559,11 +561,18 @@ template void launch_prep_dens<double>(const BinPtrs&, const Scheme&, const swsp
                                        hipStream_t);
 
 // Pyramid of per-cell maxima of the support radius H = eps h, levels 0..k
-// of every box.  Particles are in Morton order, so the particles of a cell
-// at any level are consecutive: per level, a wavefront takes the maximum
-// over each run of lanes in the same cell (segmented scan with lane
-// shuffles) and only the last lane of a run raises the cell (atomic max,
-// skipped when the cell already holds as much).
+// of every box, in two passes.  The fine levels (HMAX_TOP + 1 .. k, and
+// always level k) come from the particles: they are in Morton order, so the
+// particles of a cell at any level are consecutive, and per level a
+// wavefront takes the maximum over each run of lanes in the same cell
+// (segmented scan with lane shuffles); only the last lane of a run raises
+// the cell (atomic max, skipped when the cell already holds as much).  The
+// coarse levels (at most 8^HMAX_TOP cells each) are then reduced from their
+// children, one workgroup per box, level by level: the fine pass thus never
+// has the whole grid contend for the few coarse cells.
+constexpr int HMAX_TOP = 4;
+
+__device__ __forceinline__ int hmax_fine_lo(int k) { return k < HMAX_TOP + 1 ? k : HMAX_TOP + 1; }
 template <typename T>
 __global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
                        const uint32_t* __restrict__ keys, int32_t n_box,
@@ -582,13 +591,14 @@ __global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
     }
     const BoxInfo bi = boxtab[b];
     const int k = bi.k < 10 ? bi.k : 10;
-    // all lanes run every level of the deepest box in the wavefront
-    const int kmax = wave_max(have ? k : 0);
+    // all lanes run every fine level of the deepest box in the wavefront
+    const int kmax = wave_max(have ? k - hmax_fine_lo(k) : 0);
     for (int up = 0; up <= kmax; ++up) {
         const int l = k - up;
         // cell id at this level; lanes past their box's root or without a
         // particle get ids no other lane has
-        const uint64_t cell = (have && l >= 0)
+        const bool mine = have && l >= hmax_fine_lo(k);
+        const uint64_t cell = mine
             ? ((uint64_t)b << 32) | (uint64_t)(mort >> (3 * (k - l)))
             : ~(uint64_t)lane;
         float v = H;
@@ -600,9 +610,32 @@ __global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
         }
         const uint64_t next = __shfl_down(cell, 1, WAVE);
         const bool tail = lane == WAVE - 1 || next != cell;
-        if (have && l >= 0 && tail) {
+        if (mine && tail) {
             float* c = &pyr[bi.pyr_off + pyr_level_off(l) + (mort >> (3 * (k - l)))];
             if (*c < v) atomicMax((int*)c, __float_as_int(v));
+        }
+    }
+}
+
+// The coarse levels hmax_fine_lo(k) - 1 .. 0 of each box from their
+// children (cell c of level l has children 8c .. 8c + 7 at level l + 1).
+__global__ void __launch_bounds__(256) k_hmax_coarse(int32_t n_box,
+                                                     const BoxInfo* __restrict__ boxtab,
+                                                     float* __restrict__ pyr) {
+    for (int b = blockIdx.x; b < n_box; b += gridDim.x) {
+        const BoxInfo bi = boxtab[b];
+        const int k = bi.k < 10 ? bi.k : 10;
+        for (int l = hmax_fine_lo(k) - 1; l >= 0; --l) {
+            float* lv = pyr + bi.pyr_off + pyr_level_off(l);
+            const float* ch = pyr + bi.pyr_off + pyr_level_off(l + 1);
+            const int64_t nc = int64_t(1) << (3 * l);
+            for (int64_t c = threadIdx.x; c < nc; c += blockDim.x) {
+                float v = 0.f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v = fmaxf(v, ch[8 * c + j]);
+                lv[c] = v;
+            }
+            __syncthreads();  // level l complete before level l - 1 reads it
         }
     }
 }
@@ -613,6 +646,9 @@ void launch_hmax_pyramid(const BinPtrs& b, const Scheme& sc, hipStream_t s) {
     if (b.n <= 0) return;
     hipLaunchKernelGGL(k_hmax<T>, dim3((unsigned)((b.n + 255) / 256)), dim3(256), 0, s, b.n,
                        b.perm, b.keys, b.n_box, b.boxtab, (const T*)b.hs, (T)sc.eps, b.hmaxpyr);
+    const unsigned g = (unsigned)std::min<int64_t>(b.n_box, 4096);
+    hipLaunchKernelGGL(k_hmax_coarse, dim3(g > 0 ? g : 1), dim3(256), 0, s, b.n_box, b.boxtab,
+                       b.hmaxpyr);
 }
 template void launch_hmax_pyramid<float>(const BinPtrs&, const Scheme&, hipStream_t);
 template void launch_hmax_pyramid<double>(const BinPtrs&, const Scheme&, hipStream_t);
