@@ -72,7 +72,7 @@ struct TaskWindow {
 // together, so a wavefront waits for one memory round trip per U x 64
 // candidates instead of one per 64.  visit(have, j, code, pos, h_j) is called
 // by the whole wavefront (it may ballot); lanes past the end get have=false.
-constexpr int CAND_U = 4;
+constexpr int CAND_U = 8;
 
 template <typename T, bool NEEDH, typename F>
 __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_t* lpre, int nl,
@@ -270,7 +270,7 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
 // One wavefront per tile; tiles are popped from the item queue (for_each_item).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TASK_WPB * WAVE)
-SWSPH_WAVES_PER_EU(sizeof(T) == 4 ? 5 : 1) k_tasks(TArgs<T> a, int fixup) {
+SWSPH_WAVES_PER_EU(sizeof(T) == 4 ? 4 : 1) k_tasks(TArgs<T> a, int fixup) {
     __shared__ TaskMem smem_task[TASK_WPB];
     const int wave = threadIdx.x / WAVE;
     TaskMem& m = smem_task[wave];
