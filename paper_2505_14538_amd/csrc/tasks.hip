@@ -72,7 +72,7 @@ struct TaskWindow {
 // together, so a wavefront waits for one memory round trip per U x 64
 // candidates instead of one per 64.  visit(have, j, code, pos, h_j) is called
 // by the whole wavefront (it may ballot); lanes past the end get have=false.
-constexpr int CAND_U = 8;
+constexpr int CAND_U = 16;
 
 template <typename T, bool NEEDH, typename F>
 __device__ __forceinline__ void for_candidates(const SearchMem& sm, const int32_t* lpre, int nl,
@@ -268,9 +268,13 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
 // MODE: 0 density (radius eps*hmax*margin), 1 gradient (eps*hmax),
 // 2 force (eps*hmax, and cells whose own support reaches the tile).
 // One wavefront per tile; tiles are popped from the item queue (for_each_item).
+// The builds wait on dependent loads: 16 x 64 candidate loads in flight per
+// wavefront hide more of that than more wavefronts with fewer loads each, so
+// the register budget allows three wavefronts per SIMD (two for the force
+// build, which also loads h_j) and no spills.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TASK_WPB * WAVE)
-SWSPH_WAVES_PER_EU(sizeof(T) == 4 ? 4 : 1) k_tasks(TArgs<T> a, int fixup) {
+SWSPH_WAVES_PER_EU(sizeof(T) != 4 ? 1 : (MODE == 2 ? 2 : 3)) k_tasks(TArgs<T> a, int fixup) {
     __shared__ TaskMem smem_task[TASK_WPB];
     const int wave = threadIdx.x / WAVE;
     TaskMem& m = smem_task[wave];
