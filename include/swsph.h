@@ -108,7 +108,8 @@ typedef struct swsph_config {
     int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 128) */
     int32_t order;       /* task order: 0 cost-descending, 1 Morton cut into one
                             segment per XCD (default) */
-    int32_t leaf_max;    /* cell search: refine cells with more particles (0: 64) */
+    int32_t leaf_max;    /* cell search: refine cells with more particles (0: 64;
+                            the density task builds use 8x this, at most 4096) */
     int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 8) */
     int32_t lds_cap_dens; /* staged j-particles per wavefront, density loop (0: 256) */
     int32_t reserved[3];

@@ -438,6 +438,12 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     if (b.n <= 0) return;
     const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? DENS_MARGIN : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
+    // the density builds stop refining at 8x larger cells: their search (a
+    // chain of dependent cell-table loads, most of the build's time) gets
+    // shallower and the walk over the leaves' particles, which culls each
+    // one exactly, costs less than the levels it saves; the force build,
+    // whose cells also pass on their largest support, keeps leaf_max
+    if (mode == 0) a.leaf_max = std::min(sc.leaf_max * 8, 4096);
     if (fixup) {
         // the flagged density tiles, compacted by k_fix_list
         a.list = b.tmpidx;
