@@ -99,25 +99,19 @@ def cpu_baseline(parts):
 
 
 def per_task_step(S, dp, n_tiles, tuning):
-    """One step with one kernel launch per tile task (the same tile bodies):
-    the per-task offload baseline."""
+    """One step with one kernel launch per tile task (the same tile bodies
+    and the same work as the batched step: bin, density, and one joint
+    gradient + force pass): the per-task offload baseline."""
     import torch
-    log("per-task launch step (%d tasks per loop)" % n_tiles)
+    log("per-task launch step (%d gradient/force tasks)" % n_tiles)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     pt = S.Plan(flags=S.PER_TASK_LAUNCH, **tuning)
     torch.cuda.synchronize()
     ev0.record()
-    pt.bin(dp)
-    dd = pt.density(dp)
-    torch.cuda.synchronize()
-    log("  density done")
-    pt.gradient(dp, dd)
-    torch.cuda.synchronize()
-    log("  gradient done")
-    pt.force(dp, dd)
+    pt.step(dp)
     ev1.record()
     torch.cuda.synchronize()
-    log("  force done")
+    log("  per-task step done")
     return ev0.elapsed_time(ev1) / 1e3
 
 

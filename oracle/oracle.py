@@ -99,6 +99,10 @@ def lib():
                                     ctypes.c_int, ctypes.c_double, ctypes.c_void_p, i64,
                                     i64p, i32p, i32p]
         L.orc_count_f32.restype = i64
+        L.orc_count_f32_sym.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_void_p, i32p,
+                                        i32p]
+        L.orc_count_f32_sym.restype = i64
         L.orc_loss_subset.argtypes = [i64] + [f64p] * 8 + [ctypes.c_double, pp, f64p,
                                                            ctypes.c_double, i64, i64p,
                                                            f64p, f64p, f64p, f64p, f64p]
@@ -248,6 +252,29 @@ def count_f32(p, h32, eps: float = 2.0, idx=None, mode: str = "cells", ncell: in
         c1[ib[li]] = a
         if symmetric:
             c2[ib[li]] = b
+    return c1, c2
+
+
+def count_f32_sym(p, h32, eps: float = 2.0, mode: str = "cells", ncell: int = 0):
+    """The counts of count_f32 for every particle, the force predicate
+    enumerated from both sides of each pair (each particle searches only its
+    own support): suited to sets whose supports span orders of magnitude."""
+    n = p.n
+    c1 = np.full(n, -1, dtype=np.int32)
+    c2 = np.full(n, -1, dtype=np.int32)
+    h32 = np.ascontiguousarray(np.asarray(h32, dtype=np.float32))
+    for ib, _, _, L in _boxes(p, None):
+        arr = [_d(a[ib]) for a in (p.x, p.y, p.z)]
+        hb = np.ascontiguousarray(h32[ib])
+        a = np.empty(ib.size, dtype=np.int32)
+        b = np.empty(ib.size, dtype=np.int32)
+        r = lib().orc_count_f32_sym(ib.size, *[_ptr(x) for x in arr], L,
+                                    0 if mode == "brute" else 1, int(ncell), float(eps),
+                                    hb.ctypes.data, _ptr(a), _ptr(b))
+        if r < 0:
+            raise MemoryError("oracle count failed")
+        c1[ib] = a
+        c2[ib] = b
     return c1, c2
 
 

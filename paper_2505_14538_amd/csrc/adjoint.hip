@@ -49,7 +49,7 @@ template <typename T> __device__ __forceinline__ T m4_d2w(T q) {
 template <typename T> struct AdjPtrs {
     T* base;
     int64_t n;
-    __device__ __forceinline__ T* arr(int k) const { return base + (int64_t)k * n; }
+    __device__ __forceinline__ T* arr(int k) const { return base + (int64_t)k * adj_stride(n); }
 };
 
 // ------------------------------------------------------------------ pass A
@@ -382,11 +382,12 @@ __global__ void k_adj_prep(int64_t n, const int32_t* __restrict__ perm, const T*
                            const T* __restrict__ wc, const T* __restrict__ wcdh, T* __restrict__ J) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
+    const int64_t st = adj_stride(n);
     const int32_t p = perm[s];
     ((V4<T>*)J)[s] = V4<T>{gax[p], gay[p], gaz[p], gdu[p]};
-    J[AJ_RHODH * n + s] = rho_dh[p];
-    J[AJ_WC * n + s] = wc[p];
-    J[AJ_WCDH * n + s] = wcdh[p];
+    J[AJ_RHODH * st + s] = rho_dh[p];
+    J[AJ_WC * st + s] = wc[p];
+    J[AJ_WCDH * st + s] = wcdh[p];
 }
 
 // Pass B: chain through A, c, f = 1/Omega and Omega (per particle).
@@ -396,24 +397,25 @@ __global__ void k_adj_b(int64_t n, const V4<T>* __restrict__ pos4, const V4<T>* 
                         T* __restrict__ J) {
     int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
+    const int64_t st = adj_stride(n);
     const V4<T> d = dens4[s];  // (rho, f, c, A)
     const T u = vel4[s].w, h = hs[s], rho = d.x, f = d.y, c = d.z, A = d.w;
-    const T rhop = J[AJ_RHODH * n + s];
-    const T gA = J[AJ_GA * n + s];
+    const T rhop = J[AJ_RHODH * st + s];
+    const T gA = J[AJ_GA * st + s];
     const T gm1 = gamma - (T)1;
     T gu = gA * f * gm1 / rho;
-    if (c > (T)0) gu += J[AJ_GC * n + s] * gamma * gm1 / ((T)2 * c);
-    const T gf = J[AJ_GF * n + s] + gA * gm1 * u / rho;
-    T grho = J[AJ_GRHO * n + s] - gA * A / rho;
+    if (c > (T)0) gu += J[AJ_GC * st + s] * gamma * gm1 / ((T)2 * c);
+    const T gf = J[AJ_GF * st + s] + gA * gm1 * u / rho;
+    T grho = J[AJ_GRHO * st + s] - gA * A / rho;
     const T gOm = -gf * f * f;
-    const T gh = J[AJ_GH * n + s] + gOm * rhop / ((T)3 * rho);
+    const T gh = J[AJ_GH * st + s] + gOm * rhop / ((T)3 * rho);
     const T grhop = gOm * h / ((T)3 * rho);
     grho += -gOm * h * rhop / ((T)3 * rho * rho);
-    J[AJ_GU * n + s] = gu;
-    J[AJ_GRHO * n + s] = grho;
-    J[AJ_GRHOP * n + s] = grhop;
-    J[AJ_GH * n + s] = gh;
-    ((V4<T>*)(J + AJ_AUXC * n))[s] = V4<T>{pos4[s].w, grho, grhop, (T)1 / (eps * h)};
+    J[AJ_GU * st + s] = gu;
+    J[AJ_GRHO * st + s] = grho;
+    J[AJ_GRHOP * st + s] = grhop;
+    J[AJ_GH * st + s] = gh;
+    ((V4<T>*)(J + AJ_AUXC * st))[s] = V4<T>{pos4[s].w, grho, grhop, (T)1 / (eps * h)};
 }
 
 template <typename T>
@@ -439,9 +441,9 @@ int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* 
     hipLaunchKernelGGL(k_adj_b<T>, dim3(blocks), dim3(256), 0, s, n, (const V4<T>*)b.pos4,
                        (const V4<T>*)b.vel4, (const V4<T>*)b.dens4, (const T*)b.hs, (T)sc.gamma,
                        (T)sc.eps, J);
-    a.aux4 = (const V4<T>*)(J + AJ_AUXC * n);
+    a.aux4 = (const V4<T>*)(J + AJ_AUXC * adj_stride(n));
     r |= launch_adj<L_ADJC, T>(a, mode, lds_cap, s);
-    a.aux4 = (const V4<T>*)(J + AJ_AUXD * n);
+    a.aux4 = (const V4<T>*)(J + AJ_AUXD * adj_stride(n));
     r |= launch_adj<L_ADJD, T>(a, mode, lds_cap, s);
     return r;
 }

@@ -45,6 +45,7 @@ struct Geometry {
     int64_t tile_cap = 0;   // most tiles the bin can make (one per particle)
     int64_t n_fine = 0, n_pyr = 0;
     int64_t cand_cap = 0;
+    int64_t build_waves = 0;  // most task-build wavefronts (each may hold one list window)
     int tsz = 4;
     std::vector<BoxInfo> boxes;
     Layout lay{};
@@ -55,13 +56,16 @@ constexpr int64_t FINE_MAX = int64_t(1) << 29;
 
 // Candidate-list capacity: 160 entries per particle (lists of cell tiles
 // hold ~30-80 per particle on the clustered and uniform sets) plus one
-// build window per wavefront that can take one (at most one per tile), below
-// 2^31 (int32 offsets).  Overflow latches SWSPH_ST_CAPACITY.
-int64_t cand_capacity(int64_t n) {
-    const int64_t waves = std::min<int64_t>(std::max<int64_t>(n, 1),
-                                            (int64_t)device_cu_count() * BUILD_WAVES_PER_CU);
+// build window per wavefront that can take one (at most one per tile, at
+// most `waves` build wavefronts), below 2^31 (int32 offsets).  Overflow
+// latches SWSPH_ST_CAPACITY.
+int64_t cand_capacity(int64_t n, int64_t build_waves) {
+    const int64_t waves = std::min<int64_t>(std::max<int64_t>(n, 1), build_waves);
     return std::min<int64_t>(160 * n + 65536 + waves * TASK_CHUNK, (int64_t(1) << 31) - 1);
 }
+
+// Build wavefronts of a plain plan: BUILD_WAVES_PER_CU per CU.
+int64_t default_build_waves() { return (int64_t)device_cu_count() * BUILD_WAVES_PER_CU; }
 
 int choose_k(int64_t nb) {
     // finest grid with about one cell per particle or more (8^k <= 8 nb)
@@ -71,7 +75,7 @@ int choose_k(int64_t nb) {
 }
 
 int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_count,
-                   const double* box_size, int tile, int tile_d, int tsz) {
+                   const double* box_size, int tile, int tile_d, int tsz, int64_t build_waves) {
     if (n < 0) return fail(SWSPH_E_ARG, "n must be >= 0 (got %lld)", (long long)n);
     if (n > (int64_t(1) << 26)) return fail(SWSPH_E_ARG, "n too large (max 2^26)");
     if (n_box < 1) return fail(SWSPH_E_ARG, "n_box must be >= 1");
@@ -143,7 +147,8 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.ord_base = take(4 * (uint64_t)(order_table_size(toff) + 1));
     l.cand_cnt = take(4 * (uint64_t)(toff + 1));
     l.cand_off = take(4 * (uint64_t)(toff + 2));
-    G.cand_cap = cand_capacity(n);
+    G.build_waves = build_waves;
+    G.cand_cap = cand_capacity(n, build_waves);
     l.cands = take(4 * (uint64_t)G.cand_cap);
     l.trad = take(4 * (uint64_t)toff);
     l.tflag = take(4 * (uint64_t)toff);
@@ -152,7 +157,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.g_out = take(2 * T * N);
     l.f_out = take(4 * T * N);
     l.f_int = take(4 * N);
-    l.adj = take(32 * T * N);
+    l.adj = take(32 * T * (uint64_t)adj_stride(n));
     l.total = o;
     return SWSPH_OK;
 }
@@ -306,6 +311,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.cand_off = (int32_t*)(w + l.cand_off);
     b.cands = (uint32_t*)(w + l.cands);
     b.cand_cap = pl->G.cand_cap;
+    b.build_waves = pl->G.build_waves;
     b.trad = (float*)(w + l.trad);
     b.tflag = (int32_t*)(w + l.tflag);
     b.d_out = w + l.d_out;
@@ -431,7 +437,7 @@ int swsph_workspace_bytes(const swsph_plan* pl, int64_t n, int32_t n_box, const 
     if (!pl || !bytes) return fail(SWSPH_E_ARG, "plan and bytes are required");
     Geometry G;
     int r = build_geometry(G, n, n_box, box_count, box_size, pl->tile, pl->tile_d,
-                           pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
+                           pl->cfg.dtype == SWSPH_F64 ? 8 : 4, default_build_waves());
     if (r) return r;
     *bytes = G.lay.total;
     return SWSPH_OK;
@@ -443,7 +449,8 @@ namespace {
 
 // swsph_bin in three parts: host checks and geometry (plan state), the box
 // table upload, and the binning kernels (capturable: no host memory).
-int bin_prepare(swsph_plan* pl, const swsph_particles* p, void* ws) {
+int bin_prepare(swsph_plan* pl, const swsph_particles* p, void* ws,
+                int64_t build_waves = default_build_waves()) {
     int r = check_particles(pl, p, false);
     if (r) return r;
     if (!ws) return fail(SWSPH_E_ARG, "workspace is NULL");
@@ -451,7 +458,7 @@ int bin_prepare(swsph_plan* pl, const swsph_particles* p, void* ws) {
     Geometry G;
     const int64_t one = p->n;
     r = build_geometry(G, p->n, p->n_box, p->box_count ? p->box_count : &one, p->box_size,
-                       pl->tile, pl->tile_d, pl->cfg.dtype == SWSPH_F64 ? 8 : 4);
+                       pl->tile, pl->tile_d, pl->cfg.dtype == SWSPH_F64 ? 8 : 4, build_waves);
     if (r) return r;
     pl->G = G;
     pl->ws = ws;
@@ -476,6 +483,7 @@ void bin_enqueue(swsph_plan* pl, const swsph_particles* p, hipStream_t s) {
     if (f64) launch_keys<double>(p, b.boxtab, b.keys, b.slot, b.fine_count, b.cnt, s);
     else launch_keys<float>(p, b.boxtab, b.keys, b.slot, b.fine_count, b.cnt, s);
     launch_exclusive_scan(b.fine_count, G.n_fine, b.scan_part, b.cstart, s);
+    launch_box_check(G.n_box, b.boxtab, b.cstart, b.cnt, s);
     launch_scatter_stable(G.n, b.keys, b.slot, b.cstart, b.tmpidx, b.perm, b.rank, b.cnt, s);
     if (f64) {
         launch_gather<double>(p, b.boxtab, b.keys, b.cstart, b.perm, pl->cfg.eta, b.pos4, b.vel4,
@@ -758,7 +766,14 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
         }
         pl->gkey = std::move(key);
     } else {
-        ++pl->bin_id;
+        // Another bin on this plan (an eager call, or swsph_bin of other
+        // particles) may have rewritten the plan's geometry and the box
+        // table in the workspace since the capture: restore both for the
+        // captured particles before the replay reads them.
+        r = bin_prepare(pl, p, ws);
+        if (r) return r;
+        r = bin_upload(pl, s);
+        if (r) return r;
     }
     return hip_check(hipGraphLaunch(pl->exec, s), "graph launch");
 }
@@ -784,11 +799,11 @@ int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_d
     if (pl->cfg.dtype == SWSPH_F64) {
         r = launch_backward<double>(b, sc, g, d, pl->lds_cap, s);
         for (int k = 0; k < 8; ++k)
-            launch_unsort<double>(n, b.rank, (double*)b.adj + src[k] * n, dst[k], s);
+            launch_unsort<double>(n, b.rank, (double*)b.adj + src[k] * adj_stride(n), dst[k], s);
     } else {
         r = launch_backward<float>(b, sc, g, d, pl->lds_cap, s);
         for (int k = 0; k < 8; ++k)
-            launch_unsort<float>(n, b.rank, (float*)b.adj + src[k] * n, dst[k], s);
+            launch_unsort<float>(n, b.rank, (float*)b.adj + src[k] * adj_stride(n), dst[k], s);
     }
     if (r) return fail(SWSPH_E_HIP, "backward kernel launch failed");
     return hip_check(hipGetLastError(), "force_backward");

@@ -12,6 +12,8 @@
 // each particle a slot inside its cell), exclusive scan, scatter, and a
 // deterministic fix-up that orders the particles of each fine cell by their
 // input index (so the result is independent of atomic timing).
+#include <algorithm>
+
 #include "launch.h"
 
 namespace swsph {
@@ -185,6 +187,27 @@ void launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* part, int32_t*
     hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, part, out);
 }
 
+// The particles each box received (from the scanned fine histogram) against
+// the counts the caller declared on the host.  A mismatch means box_id and
+// box_count disagree: the bin stays self-consistent (every kernel derives a
+// particle's box from its cell key), but the result is not what the caller
+// described, so it is reported as SWSPH_ST_DOMAIN.
+__global__ void k_box_check(int32_t n_box, const BoxInfo* __restrict__ boxtab,
+                            const int32_t* __restrict__ cstart, Counters* __restrict__ cnt) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_box; b += gridDim.x * blockDim.x) {
+        const BoxInfo bi = boxtab[b];
+        const int64_t fb = bi.fine_off, fe = fb + (int64_t(1) << (3 * bi.k));
+        if ((int64_t)(cstart[fe] - cstart[fb]) != bi.count) latch(cnt, SWSPH_ST_DOMAIN);
+    }
+}
+
+void launch_box_check(int32_t n_box, const BoxInfo* boxtab, const int32_t* cstart, Counters* cnt,
+                      hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>((n_box + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_box_check, dim3(g > 0 ? g : 1), dim3(256), 0, s, n_box, boxtab, cstart,
+                       cnt);
+}
+
 // ------------------------------------------------------- scatter + fix-up
 
 __global__ void k_scatter(int64_t n, const uint32_t* __restrict__ keys,
@@ -240,7 +263,7 @@ __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict
                          const T* __restrict__ z, const T* __restrict__ vx,
                          const T* __restrict__ vy, const T* __restrict__ vz,
                          const T* __restrict__ u, const T* __restrict__ m,
-                         const T* __restrict__ hin, const int32_t* __restrict__ box_id,
+                         const T* __restrict__ hin, int32_t n_box,
                          const BoxInfo* __restrict__ boxtab, const uint32_t* __restrict__ keys,
                          const int32_t* __restrict__ cstart, const int32_t* __restrict__ perm,
                          double eta, V4<T>* __restrict__ pos4, V4<T>* __restrict__ vel4,
@@ -257,8 +280,9 @@ __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict
     if (hin) {
         h = hin[p];
     } else {
-        const BoxInfo bi = boxtab[box_id ? box_id[p] : 0];
-        uint32_t mort = keys[p] - (uint32_t)bi.fine_off;
+        const uint32_t key = keys[p];
+        const BoxInfo bi = boxtab[box_of_key(key, n_box, boxtab)];
+        uint32_t mort = key - (uint32_t)bi.fine_off;
         const int k = bi.k < 10 ? bi.k : 10;
         int lev = k;
         int64_t cntl = 0, child = 0;
@@ -295,7 +319,7 @@ void launch_gather(const swsph_particles* p, const BoxInfo* boxtab, const uint32
     hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        (const T*)p->x, (const T*)p->y, (const T*)p->z, (const T*)p->vx,
                        (const T*)p->vy, (const T*)p->vz, (const T*)p->u, (const T*)p->m,
-                       (const T*)p->h, p->box_id, boxtab, keys, cstart, perm, eta,
+                       (const T*)p->h, p->n_box, boxtab, keys, cstart, perm, eta,
                        (V4<T>*)pos4, (V4<T>*)vel4, (T*)hs);
 }
 template void launch_gather<float>(const swsph_particles*, const BoxInfo*, const uint32_t*,
@@ -336,8 +360,9 @@ __global__ void k_tile_flags(int64_t n, int32_t n_box, const BoxInfo* __restrict
                              int32_t* __restrict__ flag) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const BoxInfo bi = boxtab[box_of_sorted(s, n_box, boxtab)];
-    const uint32_t mort = keys[perm[s]] - (uint32_t)bi.fine_off;
+    const uint32_t key = keys[perm[s]];
+    const BoxInfo bi = boxtab[box_of_key(key, n_box, boxtab)];
+    const uint32_t mort = key - (uint32_t)bi.fine_off;
     int64_t cbeg = s, cend = s + 1;
     tile_cell(s, bi, mort, cstart, tile, cbeg, cend);
     flag[s] = ((s - cbeg) % tile) == 0 ? 1 : 0;
@@ -352,9 +377,10 @@ __global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict_
     if (s >= n) return;
     if (s == n - 1) *ntiles = (unsigned long long)tidx[n];
     if (!flag[s]) return;
-    const int b = box_of_sorted(s, n_box, boxtab);
+    const uint32_t key = keys[perm[s]];
+    const int b = box_of_key(key, n_box, boxtab);
     const BoxInfo bi = boxtab[b];
-    const uint32_t mort = keys[perm[s]] - (uint32_t)bi.fine_off;
+    const uint32_t mort = key - (uint32_t)bi.fine_off;
     int64_t cbeg = s, cend = s + 1;
     tile_cell(s, bi, mort, cstart, tile, cbeg, cend);
     Tile tl;
@@ -363,6 +389,21 @@ __global__ void k_tile_make(int64_t n, int32_t n_box, const BoxInfo* __restrict_
     tl.box = b;
     tl.flags = 0;
     tiles[tidx[s]] = tl;
+}
+
+// A coordinate narrowed to float without moving it inward: lo bounds round
+// down, hi bounds up (exact for float data; for double data the float box
+// still contains every particle, so distances to it never exceed the true
+// ones and no cull built on it can drop a pair at the support edge).
+__device__ __forceinline__ float narrow_lo(float v) { return v; }
+__device__ __forceinline__ float narrow_hi(float v) { return v; }
+__device__ __forceinline__ float narrow_lo(double v) {
+    const float f = (float)v;
+    return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float narrow_hi(double v) {
+    const float f = (float)v;
+    return (double)f < v ? nextafterf(f, INFINITY) : f;
 }
 
 // The bounding box and largest h of each tile's particles.
@@ -381,9 +422,10 @@ __global__ void k_tile_bounds(const V4<T>* __restrict__ pos4, const T* __restric
         const int cnt = tl.count < 64 ? tl.count : 64;
         for (int k = 0; k < cnt; ++k) {
             const V4<T> a = pos4[tl.begin + k];
-            const float px = (float)a.x, py = (float)a.y, pz = (float)a.z;
-            lx = fminf(lx, px); ly = fminf(ly, py); lz = fminf(lz, pz);
-            ux = fmaxf(ux, px); uy = fmaxf(uy, py); uz = fmaxf(uz, pz);
+            lx = fminf(lx, narrow_lo(a.x)); ly = fminf(ly, narrow_lo(a.y));
+            lz = fminf(lz, narrow_lo(a.z));
+            ux = fmaxf(ux, narrow_hi(a.x)); uy = fmaxf(uy, narrow_hi(a.y));
+            uz = fmaxf(uz, narrow_hi(a.z));
             hm = fmaxf(hm, (float)hs[tl.begin + k]);
         }
         tl.lo[0] = lx; tl.lo[1] = ly; tl.lo[2] = lz;

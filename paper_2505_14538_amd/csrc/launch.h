@@ -44,6 +44,7 @@ struct BinPtrs {
     int32_t *cand_cnt, *cand_off;
     uint32_t* cands;
     int64_t cand_cap;
+    int64_t build_waves;       // most task-build wavefronts (the capacity counts one window each)
     float* trad;
     int32_t* tflag;
     void *d_out, *g_out, *f_out, *adj;
@@ -69,6 +70,8 @@ void launch_keys(const swsph_particles* p, const BoxInfo* boxtab, uint32_t* keys
 int64_t scan_partials_needed(int64_t n);
 void launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* part, int32_t* out,
                            hipStream_t s);
+void launch_box_check(int32_t n_box, const BoxInfo* boxtab, const int32_t* cstart, Counters* cnt,
+                      hipStream_t s);
 void launch_scatter_stable(int64_t n, const uint32_t* keys, const int32_t* slot,
                            const int32_t* cstart, int32_t* tmpidx, int32_t* perm,
                            int32_t* rank, Counters* cnt, hipStream_t s);

@@ -585,8 +585,9 @@ __global__ void k_hmax(int64_t n, const int32_t* __restrict__ perm,
     uint32_t mort = 0;
     float H = 0.f;
     if (have) {
-        b = box_of_sorted(s, n_box, boxtab);
-        mort = keys[perm[s]] - (uint32_t)boxtab[b].fine_off;
+        const uint32_t key = keys[perm[s]];
+        b = box_of_key(key, n_box, boxtab);
+        mort = key - (uint32_t)boxtab[b].fine_off;
         H = (float)(eps * hs[s]) * (1.0f + 1e-6f);
     }
     const BoxInfo bi = boxtab[b];

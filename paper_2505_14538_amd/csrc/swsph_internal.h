@@ -256,18 +256,26 @@ __host__ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
     return v;
 }
 
+// Element stride of the adjoint's per-particle scratch arrays: n rounded up
+// to a multiple of 4, so every array (and the 4-vector views over four of
+// them) starts 4-element aligned inside the 256-byte aligned region.
+__host__ __device__ __forceinline__ int64_t adj_stride(int64_t n) { return (n + 3) & ~int64_t(3); }
+
 // Offset of level l inside one box's pyramid (levels 0..k, 8^l cells each).
 __host__ __device__ __forceinline__ int64_t pyr_level_off(int l) {
     return ((int64_t(1) << (3 * l)) - 1) / 7;
 }
 
-// Box of the binned particle s: boxes occupy consecutive ranges.
-__device__ __forceinline__ int box_of_sorted(int64_t s, int32_t n_box,
-                                             const BoxInfo* __restrict__ boxtab) {
+// Box of a cell key: the last box whose fine-cell range starts at or
+// before it (every box owns at least one fine cell, so the offsets rise
+// strictly).  Keys come from the cell table itself, so this never disagrees
+// with the binned layout, whatever per-box counts the caller declared.
+__device__ __forceinline__ int box_of_key(uint32_t key, int32_t n_box,
+                                          const BoxInfo* __restrict__ boxtab) {
     int lo = 0, hi = n_box - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (boxtab[mid].start <= s) lo = mid; else hi = mid - 1;
+        if (boxtab[mid].fine_off <= (int64_t)key) lo = mid; else hi = mid - 1;
     }
     return lo;
 }

@@ -454,9 +454,9 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
         mode == 0 ? k_tasks<T, 0> : (mode == 1 ? k_tasks<T, 1> : k_tasks<T, 2>);
     launch_fill_u32(&b.cnt->cand_used, 2, 0u, s);
     launch_fill_u32(a.heads, 2 * NSEG, 0u, s);
-    // at most BUILD_WAVES_PER_CU wavefronts per CU take windows (the
-    // candidate capacity counts on it)
-    const unsigned gmax = (unsigned)(device_cu_count() * (BUILD_WAVES_PER_CU / TASK_WPB));
+    // at most b.build_waves wavefronts take windows (the candidate capacity
+    // counts on it)
+    const unsigned gmax = (unsigned)std::max<int64_t>(1, b.build_waves / TASK_WPB);
     const unsigned grid = std::min(resident_grid((const void*)kern, TASK_WPB * WAVE), gmax);
     hipLaunchKernelGGL(kern, dim3(grid), block, 0, s, a,
                        (int)fixup);

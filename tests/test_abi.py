@@ -99,3 +99,4 @@ def test_calls_reject_bad_particles_on_host(S):
     # FIXED_H needs h
     q = S.Plan(flags=S.FIXED_H)
     assert S._lib.swsph_bin(q.h, ctypes.byref(pc), ws, None) == -1
+

@@ -40,16 +40,31 @@ def gpu_all(S, p, **kw):
     return S.host(d), S.host(g), S.host(f), st
 
 
-def check_sample(O, p, d, g, f, idx, ncell=0):
+def check_density(od, d, idx=None):
+    """Every density output against the oracle's (solved for the same
+    particles): h, rho, f and the number density within 1e-5 relative;
+    the h-derivatives, div v and curl v within 1e-4 of their largest
+    magnitude."""
+    sel = slice(None) if idx is None else idx
+    rel = lambda k: np.abs(d[k][sel].astype(np.float64) - od[k][sel]) / np.abs(od[k][sel])
+    for k in ("h", "rho", "f", "wcount"):
+        assert rel(k).max() < 1e-5, k
+    for k in ("rho_dh", "wcount_dh", "div_v", "curl_x", "curl_y", "curl_z"):
+        ref = od[k][sel]
+        scale = np.abs(ref).max()
+        err = np.abs(d[k][sel].astype(np.float64) - ref).max()
+        assert err <= 1e-4 * scale, (k, err, scale)
+
+
+def check_sample(O, p, d, g, f, idx, ncell=0, od=None):
     prm = O.Params(ncell=ncell)
-    od = O.density(p, prm)
+    if od is None:
+        od = O.density(p, prm)
     assert od["n_bad"] == 0
+    check_density(od, d, idx)
     og = O.gradient(p, od, prm, idx=idx)
     of = O.force(p, od, prm, idx=idx)
     rel = lambda a, b: np.abs(a[idx].astype(np.float64) - b[idx]) / np.abs(b[idx])
-    assert rel(d["h"], od["h"]).max() < 1e-5
-    assert rel(d["rho"], od["rho"]).max() < 1e-5
-    assert rel(d["f"], od["f"]).max() < 1e-5
     assert rel(g["v_sig"], og["v_sig"]).max() < 1e-5
     scale = np.abs(og["lap_u"][idx]).max()   # 0 when u is uniform: then both are exactly 0
     assert np.abs(g["lap_u"][idx] - og["lap_u"][idx]).max() <= 1e-4 * scale
@@ -57,6 +72,17 @@ def check_sample(O, p, d, g, f, idx, ncell=0):
         ref = of[k][idx]
         err = np.abs(f[k][idx].astype(np.float64) - ref).max() / np.abs(ref).max()
         assert err < 1e-4, (k, err)
+
+
+def check_counts(O, p, d, f, ncell=0):
+    """Neighbour counts of the density loop (r < H_i) and of the force loop
+    (r < max(H_i, H_j)) for every particle, bit for bit, against the oracle's
+    binary32 predicate at the smoothing lengths the GPU returned."""
+    c1, c2 = O.count_f32_sym(p, d["h"], ncell=ncell)
+    bad1 = np.flatnonzero(d["nngb"] != c1)
+    bad2 = np.flatnonzero(f["nint"] != c2)
+    assert bad1.size == 0, (bad1[:10], d["nngb"][bad1[:10]], c1[bad1[:10]])
+    assert bad2.size == 0, (bad2[:10], f["nint"][bad2[:10]], c2[bad2[:10]])
 
 
 def conservation(p, f, rel_tol):
@@ -70,16 +96,23 @@ def conservation(p, f, rel_tol):
 
 def test_clustered_full_size(S, oracle_mod):
     """The benchmark set (2^21 particles, h over ~44x) in the benchmark's
-    launch configuration: sampled outputs against the oracle, conservation
-    over all particles."""
+    launch configuration: every density output of every particle against
+    the oracle, the integer neighbour counts of both loops bit for bit at
+    the GPU's h, gradient and force outputs on a sample the oracle computes
+    one by one, conservation over all particles."""
     O = oracle_mod
     p = W.clustered()
     _flush("clustered n=%d" % p.n)
     d, g, f, st = gpu_all(S, p)
     assert st["code"] == 0, st
     assert np.all(d["iters"] > 0)
+    od = O.density(p, O.Params(ncell=128))
+    _flush("clustered: oracle density done")
+    check_density(od, d)
+    check_counts(O, p, d, f, ncell=128)
+    _flush("clustered: counts done")
     idx = np.sort(np.random.default_rng(11).choice(p.n, 3000, replace=False))
-    check_sample(O, p, d, g, f, idx, ncell=128)
+    check_sample(O, p, d, g, f, idx, ncell=128, od=od)
     conservation(p, f, 2e-5)
 
 
@@ -100,6 +133,7 @@ def test_many_boxes_full_size(S, oracle_mod):
         q.box_size = np.array([1.0])
         sub = lambda r: {k: v[ib] for k, v in r.items()}
         check_sample(O, q, sub(d), sub(g), sub(f), np.arange(q.n))
+        check_counts(O, q, sub(d), sub(f))
 
 
 def test_ragged_small_and_tiles(S, oracle_mod):
@@ -159,3 +193,25 @@ def test_device_errors_latched(S):
     torch.cuda.synchronize()
     st = plan.stats()
     assert st["code"] in (-5, -6) and st["status"] & S.ST_REACH
+
+
+def test_box_count_mismatch_reported(S):
+    """box_id and the declared per-box counts disagree: the bin stays
+    self-consistent (a particle's box comes from its cell key) and the
+    mismatch is reported as SWSPH_E_DOMAIN."""
+    import torch
+    p = W.many_boxes(n_box=3, nmin=2048, nmax=4096)
+    dp = S.to_device(p)
+    counts = np.asarray(dp.box_count).copy()
+    assert counts.size == 3 and counts[0] > 10
+    counts[0] -= 7
+    counts[1] += 7            # same total, wrong split
+    dp.box_count = counts
+    _flush("box count mismatch: counts %s" % counts.tolist())
+    plan = S.Plan()
+    plan.bin(dp)
+    d = plan.density(dp)
+    plan.force(dp, d)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    assert st["code"] == -7 and st["status"] & S.ST_DOMAIN, st

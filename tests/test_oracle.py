@@ -425,3 +425,84 @@ def test_viscosity_uniform_compression(oracle_mod):
     P = (GAMMA - 1) * d["rho"] * 1.0
     pred_p = 3 * s * d["f"] * P / d["rho"]
     assert np.abs(f0["dudt"][inner] / pred_p[inner] - 1).max() < 0.03
+
+
+def test_count_f32_sym_equals_brute(oracle_mod):
+    """The two-sided count (each particle searches only its own support)
+    equals the brute-force binary32 counts, on a set whose supports span
+    more than an order of magnitude, including pairs across the periodic
+    seam."""
+    O = oracle_mod
+    rng = np.random.default_rng(17)
+    n = 700
+    pts = rng.uniform(0, 1, size=(n, 3))
+    p = W._pack(pts, np.zeros_like(pts), np.ones(n), np.full(n, 1.0 / n), 1.0, "rand", 0)
+    h32 = np.exp(rng.uniform(np.log(0.006), np.log(0.12), n)).astype(np.float32)
+    a1, a2 = O.count_f32(p, h32, mode="brute")
+    for mode, nc in (("brute", 0), ("cells", 3), ("cells", 0)):
+        b1, b2 = O.count_f32_sym(p, h32, mode=mode, ncell=nc)
+        assert np.array_equal(a1, b1), mode
+        assert np.array_equal(a2, b2), mode
+    assert np.any(a2 > a1)   # some pairs are inside only the neighbour's support
+
+
+def _two_particles(O, x1, x2, v1, v2, u1, u2, h):
+    pts = np.array([x1, x2], dtype=np.float64)
+    vel = np.array([v1, v2], dtype=np.float64)
+    p = W._pack(pts, vel, np.array([u1, u2]), np.full(2, 0.5), 1.0, "pair", 0)
+    p = as64(p)
+    dens = {"h": np.full(2, h), "rho": np.ones(2)}
+    return O.gradient(p, dens)
+
+
+def test_signal_speed_two_particle_closed_form(oracle_mod):
+    """Eq. 10-11 on one pair inside each other's support: approaching head on,
+    v_sig = c_i + c_j + beta |v_ij . r_hat| (the radial closing speed, not
+    v_ij . r_ij); receding, or moving across the line of centres, mu = 0 and
+    v_sig = max(2 c_i, c_i + c_j)."""
+    O = oracle_mod
+    beta = O.Params().beta
+    # every input is dyadic, hence exact in the float32 particle arrays
+    u1, u2 = 0.75, 2.875
+    c1, c2 = (np.sqrt(GAMMA * (GAMMA - 1) * u) for u in (u1, u2))
+    x1, x2 = (0.375, 0.5, 0.5), (0.625, 0.5, 0.5)   # r = 0.25 along x
+    h = 0.1875                                      # support 0.375 > r
+    # approaching: closing speed 0.25 + 0.125 = 0.375
+    g = _two_particles(O, x1, x2, (0.25, 0, 0), (-0.125, 0, 0), u1, u2, h)
+    want = c1 + c2 + beta * 0.375
+    assert abs(g["v_sig"][0] - want) < 1e-12 * want
+    assert abs(g["v_sig"][1] - want) < 1e-12 * want
+    # an oblique approach: only the radial part counts
+    g = _two_particles(O, x1, x2, (0.25, 0.5, -0.125), (-0.125, 0.5, -0.125), u1, u2, h)
+    assert abs(g["v_sig"][0] - want) < 1e-12 * want
+    # receding: mu = 0
+    g = _two_particles(O, x1, x2, (-0.25, 0, 0), (0.125, 0, 0), u1, u2, h)
+    assert abs(g["v_sig"][0] - max(2 * c1, c1 + c2)) < 1e-12 * c2
+    assert abs(g["v_sig"][1] - max(2 * c2, c1 + c2)) < 1e-12 * c2
+    # transverse motion: mu = 0
+    g = _two_particles(O, x1, x2, (0, 0.5, 0), (0, -0.5, 0), u1, u2, h)
+    assert abs(g["v_sig"][0] - (c1 + c2)) < 1e-12 * c2
+    # outside the support: v_sig = 2 c_i whatever the velocities
+    g = _two_particles(O, x1, x2, (0.25, 0, 0), (-0.125, 0, 0), u1, u2, 0.125)
+    assert abs(g["v_sig"][0] - 2 * c1) < 1e-12 and abs(g["v_sig"][1] - 2 * c2) < 1e-12
+
+
+def test_loss_subset_equals_force_sum(oracle_mod):
+    """The finite-difference loss (density re-solved around the subset, force
+    of the subset) equals sum_i w_i . a_i + c_i du_i/dt from the density and
+    force loops over the whole set, for the whole set and for a subset."""
+    O = oracle_mod
+    p, w, c = W.diff(nside=8)
+    p = as64(p)
+    prm = O.Params(tol=1e-15, max_iter=300)
+    d = O.density(p, prm)
+    fo = O.force(p, d, prm)
+    w = w.astype(np.float64)
+    c = c.astype(np.float64)
+    per = w[:, 0] * fo["ax"] + w[:, 1] * fo["ay"] + w[:, 2] * fo["az"] + c * fo["dudt"]
+    args = (p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.m, 1.0, prm)
+    full = O.loss_subset(*args, np.arange(p.n), w[:, 0], w[:, 1], w[:, 2], c, Rbig=0.499)
+    assert abs(full - per.sum()) <= 1e-10 * np.abs(per).sum()
+    sub = np.arange(0, p.n, 7)
+    part = O.loss_subset(*args, sub, w[:, 0], w[:, 1], w[:, 2], c, Rbig=0.499)
+    assert abs(part - per[sub].sum()) <= 1e-10 * np.abs(per[sub]).sum()
