@@ -67,6 +67,32 @@ class Params:
                          0 if self.mode == "brute" else 1, int(self.ncell))
 
 
+class OrcSwitchParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("dt", "av_max", "av_min", "ell", "beta_c", "ac_min", "ac_max", "bal_eps")]
+
+
+@dataclass
+class SwitchParams:
+    """Constants of the time-dependent switches (Sec. 2.1.3-2.1.4): the decay
+    length l = 0.05 is the paper's; alpha_V,max = 2, alpha_V,min = 0,
+    beta_c = 1, alpha_c in [0, 1] and the Balsara softening 1e-4 c/H are
+    conventions (the paper gives no values)."""
+
+    dt: float = 1e-3
+    av_max: float = 2.0
+    av_min: float = 0.0
+    ell: float = 0.05
+    beta_c: float = 1.0
+    ac_min: float = 0.0
+    ac_max: float = 1.0
+    bal_eps: float = 1e-4
+
+    def c(self) -> OrcSwitchParams:
+        return OrcSwitchParams(self.dt, self.av_max, self.av_min, self.ell, self.beta_c,
+                               self.ac_min, self.ac_max, self.bal_eps)
+
+
 _lib = None
 
 
@@ -107,6 +133,17 @@ def lib():
                                                            ctypes.c_double, i64, i64p,
                                                            f64p, f64p, f64p, f64p, f64p]
         L.orc_loss_subset.restype = i64
+        sp = ctypes.POINTER(OrcSwitchParams)
+        L.orc_switch_visc.argtypes = [i64, pp, sp] + [f64p] * 11
+        L.orc_switch_visc.restype = None
+        L.orc_alpha_ngb.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double, pp, f64p, f64p,
+                                    f64p]
+        L.orc_alpha_ngb.restype = i64
+        L.orc_switch_cond.argtypes = [i64, pp, sp] + [f64p] * 7
+        L.orc_switch_cond.restype = None
+        L.orc_force_sw.argtypes = [i64] + [f64p] * 8 + [ctypes.c_double, pp] + [f64p] * 6 + \
+            [i64, i64p, f64p, f64p, f64p, f64p, i32p]
+        L.orc_force_sw.restype = i64
         _lib = L
     return _lib
 
@@ -320,3 +357,73 @@ def derived(p, dens, params: Params = Params()):
     c = np.sqrt(params.gamma * (params.gamma - 1.0) * u)
     A = dens["f"] * P / rho ** 2
     return {"P": P, "c": c, "A": A}
+
+
+def switch_visc(p, dens, sw: SwitchParams, div_prev, vsig_prev, av_in,
+                params: Params = Params()):
+    """Viscosity switch after the density loop (Eq. 12-16): returns
+    {'alpha_v': alpha_V(t + dt), 'balsara': B} per particle."""
+    n = p.n
+    h, u = _d(dens["h"]), _d(p.u)
+    args = [_d(dens[k]) for k in ("div_v",)] + [_d(div_prev)] + \
+        [_d(dens[k]) for k in ("curl_x", "curl_y", "curl_z")] + [_d(vsig_prev), _d(av_in)]
+    av = np.empty(n)
+    B = np.empty(n)
+    lib().orc_switch_visc(n, ctypes.byref(params.c()), ctypes.byref(sw.c()), _ptr(h),
+                          _ptr(u), *[_ptr(a) for a in args], _ptr(av), _ptr(B))
+    return {"alpha_v": av, "balsara": B}
+
+
+def alpha_ngb(p, dens, av, params: Params = Params()):
+    """Largest alpha_V over each particle's support r < H_i (own included)."""
+    out = np.full(p.n, np.nan)
+    av = _d(av)
+    for ib, _, _, L in _boxes(p, None):
+        arr = [_d(a[ib]) for a in (p.x, p.y, p.z)]
+        h = _d(np.asarray(dens["h"])[ib])
+        o = np.empty(ib.size)
+        a = np.ascontiguousarray(av[ib])
+        if lib().orc_alpha_ngb(ib.size, *[_ptr(x) for x in arr], L,
+                               ctypes.byref(params.c()), _ptr(h), _ptr(a), _ptr(o)) < 0:
+            raise MemoryError("oracle alpha_ngb failed")
+        out[ib] = o
+    return out
+
+
+def switch_cond(p, dens, grad, sw: SwitchParams, av_ngb, ac_in, params: Params = Params()):
+    """Conduction switch after the gradient loop (Eq. 21, 23-24): alpha_c(t+dt)."""
+    n = p.n
+    ac = np.empty(n)
+    args = [_d(dens["h"]), _d(p.u), _d(grad["v_sig"]), _d(grad["lap_u"]), _d(av_ngb),
+            _d(ac_in)]
+    lib().orc_switch_cond(n, ctypes.byref(params.c()), ctypes.byref(sw.c()),
+                          *[_ptr(a) for a in args], _ptr(ac))
+    return ac
+
+
+def force_sw(p, dens, av, B, ac, params: Params = Params(), idx=None):
+    """Force loop with the switches: alpha_ij = (av_i + av_j)/2 (B_i + B_j)/2
+    in the viscosity and artificial conduction in du/dt (Eq. 16, 19-20, 22)."""
+    n = p.n
+    res = {k: np.full(n, np.nan) for k in ("ax", "ay", "az", "dudt")}
+    res["nint"] = np.full(n, -1, dtype=np.int32)
+    idx = None if idx is None else np.asarray(idx, dtype=np.int64)
+    av, B, ac = _d(av), _d(B), _d(ac)
+    for ib, out_pos, lidx, L in _boxes(p, idx):
+        nb = ib.size
+        arr = [_d(a[ib]) for a in (p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.m)]
+        per = [_d(np.asarray(dens[k])[ib]) for k in ("h", "rho", "f")] + \
+            [np.ascontiguousarray(a[ib]) for a in (av, B, ac)]
+        loc = {k: np.full(nb, np.nan) for k in ("ax", "ay", "az", "dudt")}
+        ni = np.full(nb, -1, dtype=np.int32)
+        li = None if lidx is None else np.ascontiguousarray(lidx)
+        r = lib().orc_force_sw(nb, *[_ptr(a) for a in arr], L, ctypes.byref(params.c()),
+                               *[_ptr(a) for a in per], 0 if li is None else li.size,
+                               _ptr(li), _ptr(loc["ax"]), _ptr(loc["ay"]), _ptr(loc["az"]),
+                               _ptr(loc["dudt"]), _ptr(ni))
+        if r < 0:
+            raise MemoryError("oracle force_sw failed")
+        for k in loc:
+            res[k][ib] = loc[k]
+        res["nint"][ib] = ni
+    return res

@@ -34,6 +34,12 @@
  *               G_k = grad_i W(r_ij, h_k), mu = min(0, v_ij . r_hat),
  *               v_sig = c_i + c_j - beta mu, nu = -alpha mu v_sig/(rho_i+rho_j).
  *               Pairs: j != i with r < max(H_i, H_j).
+ *   switches    the time-dependent dissipation switches of Sec. 2.1.3-2.1.4
+ *               (Eq. 12-16 viscosity coefficient and Balsara factor, Eq. 19-24
+ *               artificial conduction): per-particle updates and the force
+ *               loop with alpha_ij and conduction (orc_switch_visc,
+ *               orc_alpha_ngb, orc_switch_cond, orc_force_sw; readings of
+ *               the garbled equations stated there).
  *
  * Conventions: r_ij = x_i - x_j - s (minimum periodic image s), v_ij = v_i - v_j.
  * The self term j = i enters n, rho and their h-derivatives, and nothing
@@ -792,4 +798,191 @@ int64_t orc_loss_subset(int64_t n, const double* x, const double* y, const doubl
     free(ax); free(ay); free(az); free(du);
     grid_free(&g);
     return bad;
+}
+
+/* ------------------------------------ time-dependent dissipation switches */
+
+/*
+ * SPHENIX-type switches (Sec. 2.1.3, Eq. 12-16; Sec. 2.1.4, Eq. 19-24),
+ * with these readings of the printed equations (several are garbled):
+ *
+ *   Eq. 13-15  S_i = H_i^2 max(0, -(div v_i(t+dt) - div v_i(t)) / dt),
+ *              alpha_loc,i = alpha_V,max S_i / (v_sig,i^2 + S_i), v_sig,i the
+ *              particle's signal speed of the previous gradient loop (the
+ *              printed dt factor on alpha_loc is dropped: alpha_loc is a
+ *              dimensionless target);
+ *   Eq. 12     alpha_V relaxes towards alpha_loc on the time scale
+ *              H_i / (l c_i): alpha(t+dt) = alpha_loc when alpha_loc >=
+ *              alpha(t), else alpha_loc + (alpha(t) - alpha_loc)
+ *              exp(-l c_i dt / H_i); then at least alpha_V,min;
+ *   Eq. 16     B_i the Balsara factor |div v| / (|div v| + |curl v| +
+ *              bal_eps c_i / H_i) (the paper names B without defining it);
+ *   Eq. 24     alpha_c,max,i = alpha_c,max (1 - alpha_V,ngb,i / alpha_V,max),
+ *              alpha_V,ngb,i the largest alpha_V over the particle's support
+ *              (its own included);
+ *   Eq. 21     d alpha_c,i / dt = beta_c H_i lap u_i / sqrt(u_i)
+ *              - (alpha_c,i - alpha_c,min) v_sig,i / H_i (the printed extra
+ *              alpha_c factor of the source term is dropped: with it
+ *              alpha_c = 0 could never switch on; v_c,i read as the
+ *              particle's signal speed); one explicit Euler step of dt,
+ *              then clamped to [alpha_c,min, alpha_c,max,i] (Eq. 23);
+ *   Eq. 20     alpha_c,ij = (P_i alpha_c,i + P_j alpha_c,j) / (P_i + P_j);
+ *   Eq. 22     v_c,ij = |v_ij . r_hat| + sqrt(2 |P_i - P_j| / (rho_i + rho_j))
+ *              (the relative velocity, so the pair term is symmetric);
+ *   Eq. 19     du_i/dt += sum_j alpha_c,ij v_c,ij m_j (u_i - u_j)
+ *              (f_i dW/dr(r,h_i) + f_j dW/dr(r,h_j)) / (rho_i + rho_j),
+ *              the kernel gradients taken as scalar radial derivatives
+ *              (negative: heat flows from the hotter particle);
+ *   Eq. 16     alpha_ij = (alpha_V,i + alpha_V,j)/2 (B_i + B_j)/2 replaces
+ *              the constant alpha in the viscosity of Eq. 9.
+ */
+typedef struct {
+    double dt;       /* time step of the switch update */
+    double av_max;   /* alpha_V,max (Eq. 13) */
+    double av_min;   /* floor of alpha_V */
+    double ell;      /* decay length l (Eq. 12; 0.05 in the paper) */
+    double beta_c;   /* beta_c (Eq. 21) */
+    double ac_min;   /* alpha_c,min (Eq. 21) */
+    double ac_max;   /* alpha_c,max (Eq. 23-24) */
+    double bal_eps;  /* Balsara softening, in units of c/H */
+} orc_switch_params;
+
+/* Viscosity switch after the density loop: alpha_V(t+dt) and B. */
+void orc_switch_visc(int64_t n, const orc_params* p, const orc_switch_params* s,
+                     const double* h, const double* u, const double* div_v,
+                     const double* div_prev, const double* cx, const double* cy,
+                     const double* cz, const double* vsig_prev, const double* av_in,
+                     double* av_out, double* B) {
+    const double gg = p->gamma * (p->gamma - 1.0);
+    for (int64_t i = 0; i < n; ++i) {
+        double H = p->eps * h[i];
+        double c = sqrt(gg * u[i]);
+        double ddiv = (div_v[i] - div_prev[i]) / s->dt;
+        double S = H * H * (ddiv < 0.0 ? -ddiv : 0.0);
+        double aloc = S > 0.0 ? s->av_max * S / (vsig_prev[i] * vsig_prev[i] + S) : 0.0;
+        double a = av_in[i];
+        if (aloc >= a) a = aloc;
+        else a = aloc + (a - aloc) * exp(-s->ell * c * s->dt / H);
+        if (a < s->av_min) a = s->av_min;
+        av_out[i] = a;
+        double d = fabs(div_v[i]);
+        double w = sqrt(cx[i] * cx[i] + cy[i] * cy[i] + cz[i] * cz[i]);
+        double den = d + w + s->bal_eps * c / H;
+        B[i] = den > 0.0 ? d / den : 0.0;
+    }
+}
+
+/* alpha_V,ngb,i = max of av_j over j with r_ij < H_i (j = i included). */
+int64_t orc_alpha_ngb(int64_t n, const double* x, const double* y, const double* z,
+                      double L, const orc_params* p, const double* h, const double* av,
+                      double* out) {
+    orc_grid g;
+    if (grid_build(&g, n, x, y, z, L, p->mode, p->ncell)) return -1;
+#pragma omp parallel
+    {
+        orc_list l = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            gather(&g, i, p->eps * h[i], NULL, 0.0, &l);
+            double v = av[i];
+            for (int64_t q = 0; q < l.n; ++q)
+                if (av[l.a[q].j] > v) v = av[l.a[q].j];
+            out[i] = v;
+        }
+        free(l.a);
+    }
+    grid_free(&g);
+    return 0;
+}
+
+/* Conduction switch after the gradient loop: alpha_c(t+dt). */
+void orc_switch_cond(int64_t n, const orc_params* p, const orc_switch_params* s,
+                     const double* h, const double* u, const double* vsig,
+                     const double* lapu, const double* av_ngb, const double* ac_in,
+                     double* ac_out) {
+    for (int64_t i = 0; i < n; ++i) {
+        double H = p->eps * h[i];
+        double src = u[i] > 0.0 ? s->beta_c * H * lapu[i] / sqrt(u[i]) : 0.0;
+        double rate = src - (ac_in[i] - s->ac_min) * vsig[i] / H;
+        double a = ac_in[i] + s->dt * rate;
+        double amax = s->ac_max * (1.0 - av_ngb[i] / s->av_max);
+        if (a > amax) a = amax;
+        if (a < s->ac_min) a = s->ac_min;
+        ac_out[i] = a;
+    }
+}
+
+/*
+ * Force loop with the switches: the viscosity of orc_force with
+ * alpha_ij = (av_i + av_j)/2 (B_i + B_j)/2, plus artificial conduction
+ * (Eq. 19-20, 22) in du/dt.  Same pairs as orc_force.
+ */
+int64_t orc_force_sw(int64_t n, const double* x, const double* y, const double* z,
+                     const double* vx, const double* vy, const double* vz,
+                     const double* u, const double* m, double L, const orc_params* p,
+                     const double* h, const double* rho, const double* f,
+                     const double* av, const double* B, const double* ac,
+                     int64_t nidx, const int64_t* idx, double* ax, double* ay,
+                     double* az, double* dudt, int32_t* nint) {
+    orc_grid g;
+    if (grid_build(&g, n, x, y, z, L, p->mode, p->ncell)) return -1;
+    const double gm1 = p->gamma - 1.0, gg = p->gamma * gm1;
+    double* Hs = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t k = 0; k < n; ++k) Hs[k] = p->eps * h[k];
+    double Hmax = max_of(Hs, n);
+    int64_t cnt = (idx ? nidx : n);
+#pragma omp parallel
+    {
+        orc_list l = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < cnt; ++k) {
+            int64_t i = idx ? idx[k] : k;
+            gather(&g, i, Hs[i], Hs, Hmax, &l);
+            double Pi = gm1 * rho[i] * u[i];
+            double Ai = f[i] * Pi / (rho[i] * rho[i]);
+            double ci = sqrt(gg * u[i]);
+            double sx = 0, sy = 0, sz = 0, su = 0;
+            int32_t c = 0;
+            for (int64_t q = 0; q < l.n; ++q) {
+                const orc_nb* v = &l.a[q];
+                int64_t j = v->j;
+                if (j == i) continue;
+                c++;
+                if (v->r == 0.0) continue;
+                double Pj = gm1 * rho[j] * u[j];
+                double Aj = f[j] * Pj / (rho[j] * rho[j]);
+                double cj = sqrt(gg * u[j]);
+                double ex = v->dx / v->r, ey = v->dy / v->r, ez = v->dz / v->r;
+                double gi = v->r < Hs[i] ? kdWdr(v->r, h[i], p->eps) : 0.0;
+                double gj = v->r < Hs[j] ? kdWdr(v->r, h[j], p->eps) : 0.0;
+                double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
+                double vdote = wx * ex + wy * ey + wz * ez;
+                double rsum = rho[i] + rho[j];
+                double nu = 0.0;
+                if (p->visc) {
+                    double mu = vdote < 0.0 ? vdote : 0.0;
+                    double vsig = ci + cj - p->beta * mu;
+                    double aij = 0.5 * (av[i] + av[j]) * 0.5 * (B[i] + B[j]);
+                    nu = -aij * mu * vsig / rsum;
+                }
+                double fg = f[i] * gi + f[j] * gj;
+                double sa = Ai * gi + Aj * gj + 0.5 * nu * fg;
+                sx -= m[j] * sa * ex;
+                sy -= m[j] * sa * ey;
+                sz -= m[j] * sa * ez;
+                su += m[j] * vdote * (Ai * gi + 0.25 * nu * fg);
+                /* artificial conduction */
+                double psum = Pi + Pj;
+                double acij = psum > 0.0 ? (Pi * ac[i] + Pj * ac[j]) / psum : 0.0;
+                double vc = fabs(vdote) + sqrt(2.0 * fabs(Pi - Pj) / rsum);
+                su += acij * vc * m[j] * (u[i] - u[j]) * fg / rsum;
+            }
+            ax[i] = sx; ay[i] = sy; az[i] = sz; dudt[i] = su;
+            if (nint) nint[i] = c;
+        }
+        free(l.a);
+    }
+    free(Hs);
+    grid_free(&g);
+    return 0;
 }
