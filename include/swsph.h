@@ -252,9 +252,30 @@ int swsph_force_backward(swsph_plan* plan, const swsph_particles* p,
 int swsph_step(swsph_plan* plan, const swsph_particles* p, swsph_density_out* d,
                swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * step as swsph_step (bin, density, gradient, force; go / fo may be NULL),
+ * run eagerly, with no workspace argument.  The library's scratch is a
+ * file-scope device array of SWSPH_STATIC_SCRATCH_BYTES (64 MiB), one copy
+ * on each GPU the library runs on, held until the process ends; its address
+ * is looked up once per device.  This call allocates nothing (no hipMalloc,
+ * no hipFree, no allocating library routine); the caller passes inputs and
+ * outputs as for swsph_step.  A particle set whose workspace would exceed
+ * the scratch (about 53,000 particles in float32, 43,000 in float64 in one
+ * box; fewer with many boxes) is rejected with SWSPH_E_ARG before any HIP
+ * call.  Every call on one GPU shares that GPU's scratch and binds the plan
+ * to it, so calls that overlap on one GPU (other streams, other threads,
+ * other plans) race: order them.  The scratch keeps the last call's contents; each call
+ * clears what it counts from.  Device conditions are read afterwards with
+ * swsph_read_stats(plan, NULL, ...). */
+#define SWSPH_STATIC_SCRATCH_BYTES (64ull << 20)
+int swsph_step_static(swsph_plan* plan, const swsph_particles* p, swsph_density_out* d,
+                      swsph_gradient_out* go, swsph_force_out* fo, void* stream);
+
 /* Copy the device statistics to the host (synchronises the stream).  The
  * return value is SWSPH_OK, or the first latched device condition as a
- * negative status (the stats are filled in either case). */
+ * negative status (the stats are filled in either case).  ws NULL: the
+ * workspace of the plan's last bin. */
 int swsph_read_stats(swsph_plan* plan, const void* ws, swsph_stats* out, void* stream);
 
 /* Time the candidate tile sizes, LDS capacities, task orders and task-search

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -632,7 +633,9 @@ int swsph_reset_timers(swsph_plan* pl) {
 }
 
 int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* stream) {
-    if (!pl || !ws || !out) return fail(SWSPH_E_ARG, "plan, ws and out are required");
+    if (!pl || !out) return fail(SWSPH_E_ARG, "plan and out are required");
+    if (!ws) ws = pl->ws;  // the workspace of the plan's last bin (swsph_step_static's scratch)
+    if (!ws) return fail(SWSPH_E_STATE, "no bin on this plan");
     if (!pl->binned || ws != pl->ws) return fail(SWSPH_E_STATE, "no bin on this workspace");
     Counters c;
     hipStream_t s = (hipStream_t)stream;
@@ -776,6 +779,85 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
         if (r) return r;
     }
     return hip_check(hipGraphLaunch(pl->exec, s), "graph launch");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Library-owned scratch of swsph_step_static: a file-scope device array, one
+// copy on every GPU the library runs on, held until the process ends.  Host
+// code never uses the array's name as an address: the device address of
+// each GPU's copy comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t STATIC_SCRATCH_BYTES = SWSPH_STATIC_SCRATCH_BYTES;
+// Task-build wavefronts of a static step: each may hold one candidate-list
+// window of TASK_CHUNK entries, so fewer of them leave the scratch to the
+// particles (the builds of small sets do not fill more).
+constexpr int64_t STATIC_BUILD_WAVES = 256;
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current GPU's scratch (looked up on first use).
+int static_scratch(void** out) {
+    int dev = 0;
+    int r = hip_check(hipGetDevice(&dev), "get device");
+    if (r) return r;
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(SWSPH_E_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        r = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (r) return r;
+        if (!ptr || ((uintptr_t)ptr) % ALIGN) return fail(SWSPH_E_HIP, "scratch address unusable");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SWSPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swsph_step_static(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
+                      swsph_gradient_out* go, swsph_force_out* fo, void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    if (!d) return fail(SWSPH_E_ARG, "density output is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    // size check before anything else (plan state and device untouched)
+    Geometry G;
+    const int64_t one = p->n;
+    r = build_geometry(G, p->n, p->n_box, p->box_count ? p->box_count : &one, p->box_size,
+                       pl->tile, pl->tile_d, pl->cfg.dtype == SWSPH_F64 ? 8 : 4,
+                       STATIC_BUILD_WAVES);
+    if (r) return r;
+    if (G.lay.total > STATIC_SCRATCH_BYTES)
+        return fail(SWSPH_E_ARG,
+                    "swsph_step_static: %lld particles need %llu bytes of scratch, more than the "
+                    "%llu bytes of the static scratch (use swsph_step with a workspace)",
+                    (long long)p->n, (unsigned long long)G.lay.total,
+                    (unsigned long long)STATIC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    r = static_scratch(&ws);
+    if (r) return r;
+    r = bin_prepare(pl, p, ws, STATIC_BUILD_WAVES);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = bin_upload(pl, s);
+    if (r) return r;
+    // the bin clears the counters, queue heads and histograms the kernels
+    // count from, so whatever a previous call left in the scratch is unused
+    bin_enqueue(pl, p, s);
+    r = hip_check(hipGetLastError(), "swsph_step_static bin");
+    if (r) return r;
+    r = swsph_density(pl, p, d, ws, stream);
+    if (r) return r;
+    if (go || fo) return gf_checked(pl, p, d, go, fo, ws, stream);
+    return SWSPH_OK;
 }
 
 int swsph_force_backward(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,

@@ -120,6 +120,8 @@ _lib.swsph_force_backward.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(Fo
                                       _P(InputGrad), _vp, _vp]
 _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut), _P(ForceOut),
                             _vp, _vp]
+_lib.swsph_step_static.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut),
+                                   _P(ForceOut), _vp]
 _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
 _lib.swsph_autotune.argtypes = [_vp, _P(ParticlesC), _vp, _vp, ctypes.c_char_p]
 _lib.swsph_plan_get_tuning.argtypes = [_vp, _P(Tuning)]
@@ -129,7 +131,7 @@ _lib.swsph_reset_timers.argtypes = [_vp]
 EXPORTS = ["swsph_version", "swsph_last_error", "swsph_config_default", "swsph_plan_create",
            "swsph_plan_destroy", "swsph_workspace_bytes", "swsph_bin", "swsph_density",
            "swsph_gradient", "swsph_force", "swsph_force_backward", "swsph_step",
-           "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
+           "swsph_step_static", "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
            "swsph_kernel_times", "swsph_reset_timers"]
 
 
@@ -356,6 +358,32 @@ class Plan:
                                self._ws_ptr(), _stream()))
         return d, g, f
 
+    def step_static(self, p: DeviceParticles, out=None):
+        """bin + density + gradient + force with the library's static device
+        scratch (swsph_step_static: no workspace, nothing allocated by the
+        library).  Outputs are fresh tensors unless `out` = (d, g, f) dicts of
+        caller tensors.  Stats afterwards: stats(static=True)."""
+        torch = _torch()
+        n = p.n
+        if out is None:
+            d = {k: self._alloc(n) for k in ("h", "rho", "rho_dh", "wcount", "wcount_dh",
+                                              "div_v", "curl_x", "curl_y", "curl_z", "f")}
+            d["nngb"] = self._alloc(n, torch.int32)
+            d["iters"] = self._alloc(n, torch.int32)
+            g = {"v_sig": self._alloc(n), "lap_u": self._alloc(n)}
+            f = {k: self._alloc(n) for k in ("ax", "ay", "az", "dudt")}
+            f["nint"] = self._alloc(n, torch.int32)
+        else:
+            d, g, f = out
+        dc = self._dens_c(d)
+        gc = GradientOut(_ptr(g["v_sig"]), _ptr(g["lap_u"])) if g else None
+        fc = ForceOut(**{k: _ptr(v) for k, v in f.items()}) if f else None
+        self._pc = p.c()
+        _check(_lib.swsph_step_static(self.h, ctypes.byref(self._pc), ctypes.byref(dc),
+                                      ctypes.byref(gc) if gc else None,
+                                      ctypes.byref(fc) if fc else None, _stream()))
+        return d, g, f
+
     def force_backward(self, p: DeviceParticles, dens, gax, gay, gaz, gdudt):
         n = p.n
         o = {k: self._alloc(n) for k in ("gx", "gy", "gz", "gvx", "gvy", "gvz", "gu", "gm")}
@@ -368,9 +396,12 @@ class Plan:
                                          _stream()))
         return o
 
-    def stats(self, check: bool = False) -> Dict:
+    def stats(self, check: bool = False, static: bool = False) -> Dict:
+        """Device statistics of the plan's last bin (static=True: of the last
+        step_static, whose scratch the library owns)."""
         s = Stats()
-        r = _lib.swsph_read_stats(self.h, self._ws_ptr(), ctypes.byref(s), _stream())
+        ws = None if static else self._ws_ptr()
+        r = _lib.swsph_read_stats(self.h, ws, ctypes.byref(s), _stream())
         if check:
             _check(r)
         d = s.as_dict()

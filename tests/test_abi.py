@@ -100,3 +100,20 @@ def test_calls_reject_bad_particles_on_host(S):
     q = S.Plan(flags=S.FIXED_H)
     assert S._lib.swsph_bin(q.h, ctypes.byref(pc), ws, None) == -1
 
+
+
+def test_static_step_rejects_oversized_set_on_host(S):
+    """swsph_step_static refuses a set whose workspace exceeds its static
+    scratch before any HIP call (this runs on a machine without a GPU)."""
+    p = S.Plan()
+    pc = S.ParticlesC()
+    pc.n = 1 << 20
+    pc.n_box = 1
+    bs = np.array([1.0])
+    pc.box_size = bs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    pc.x = pc.y = pc.z = pc.vx = pc.vy = pc.vz = pc.m = pc.u = 1024
+    d = S.DensityOut()
+    assert S._lib.swsph_step_static(p.h, ctypes.byref(pc), ctypes.byref(d), None, None,
+                                    None) == -1
+    assert b"static scratch" in S._lib.swsph_last_error()
+    assert S._lib.swsph_step_static(p.h, ctypes.byref(pc), None, None, None, None) == -1
