@@ -111,7 +111,8 @@ typedef struct swsph_config {
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: 64;
                             the density task builds use 8x this, at most 4096) */
     int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 8) */
-    int32_t lds_cap_dens; /* staged j-particles per wavefront, density loop (0: 256) */
+    int32_t lds_cap_dens; /* staged j-particles per wavefront, density loop first pass
+                             (0: 512; its fix-up passes stage up to 1024) */
     int32_t reserved[3];
 } swsph_config;
 
@@ -178,7 +179,9 @@ typedef struct swsph_stats {
     uint64_t listed;             /* candidate entries written by the task builds */
     uint64_t restages;           /* density tiles that widened their search */
     uint64_t n_tiles_dens;       /* density tile tasks of the last bin */
-    uint64_t reserved[5];
+    uint64_t dens_listed;        /* density tile passes that swept per-particle neighbour
+                                    lists (the others re-test the staged set every sweep) */
+    uint64_t reserved[4];
 } swsph_stats;
 
 typedef struct swsph_plan swsph_plan;

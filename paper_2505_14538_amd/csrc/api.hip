@@ -404,7 +404,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     pl->tile = cfg->tile ? cfg->tile : 32;
     pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 8;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
-    pl->lds_cap_d = cfg->lds_cap_dens ? cfg->lds_cap_dens : 256;
+    pl->lds_cap_d = cfg->lds_cap_dens ? cfg->lds_cap_dens : 512;
     pl->order = cfg->order;
     pl->leaf_max = cfg->leaf_max ? cfg->leaf_max : 64;
     if (cfg->flags & SWSPH_TIMING) pl->timer = new (std::nothrow) swsph::Timer();
@@ -658,6 +658,7 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
     out->listed = c.listed;
     out->restages = c.restages;
     out->n_tiles_dens = c.n_tiles_d;
+    out->dens_listed = c.dens_listed;
     if (c.status & SWSPH_ST_DOMAIN) return fail(SWSPH_E_DOMAIN, "a particle lies outside its box");
     if (c.status & SWSPH_ST_REACH) return fail(SWSPH_E_REACH, "a support radius reaches half a box");
     if (c.status & SWSPH_ST_CAPACITY) return fail(SWSPH_E_CAPACITY, "internal capacity exceeded");

@@ -29,9 +29,31 @@
 namespace swsph {
 
 // ------------------------------------------------------------ density tile
+//
+// The tile's candidates within the staged radius R of its box are staged in
+// LDS (image position and binned index).  Every i-particle then gets its own
+// list of the staged candidates within R of it -- one pass of distance
+// tests; h is held below R / eps, so the lists hold every pair any sweep can
+// reach -- and the Newton (Halley) sweeps evaluate the kernel over those
+// lists with only the sums the step needs (n and its first two log-h
+// derivatives).  One full sweep at the final h adds rho, its h-derivative,
+// div v, curl v and the neighbour count, reading the partner's mass and
+// velocity from global memory.  A tile whose candidates overflow the staging
+// buffer (or whose lists overflow) tests the staged set again every sweep,
+// staging it again as needed.
+// Lanes: c i-slots of S contiguous streams (S a power of two), so the sums
+// over a slot's streams are DPP butterflies.
+
+// Step arithmetic of the Halley update: fast hardware reciprocal and
+// exponential in FP32 (the iteration's stop test is exact, so their
+// rounding only shapes the path to the root), the library functions in FP64.
+__device__ __forceinline__ float step_rcp(float x) { return fast_rcp(x); }
+__device__ __forceinline__ double step_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float step_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double step_exp(double x) { return exp(x); }
 
 template <typename T, int CAP>
-__device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, WaveStats& ws) {
+__device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, WaveStats& ws) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
@@ -39,23 +61,22 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     if (tl.count <= 0) return;
     if (a.fixup && a.tflag[t] == 0) return;
     const int lane = lane_id();
-    const LaneMap q = lane_map(tl.count);
-    const int js = q.js, S = q.S;
-    const bool act = q.used();
+    const GroupMap q = group_map(tl.count);
+    const int js = q.js, S = q.S, c = q.c;
+    const bool act = q.act;
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + (act ? q.li : 0);
+    const int i = tl.begin + q.li;
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
-    const V4<T> vi = a.vel4[i];
     T h = a.hs[i];
     const bool fixed = (a.flags & SWSPH_FIXED_H) != 0;
     const TileGeom g = geom_of(tl);
-    const T L = (T)bi.L;
     const T Rcap = (T)(0.5f * (float)bi.L * (1.0f - 1e-6f));
     const T eps = a.eps;
     const T cnorm = (T)(8.0 / PI_D);
     // root of sum_j w(q_ij) = Tt  <=>  h^3 n(h) = eta^3
     const T Tt = a.eta * a.eta * a.eta * eps * eps * eps / cnorm;
+    const T inv_Tt = (T)1 / Tt;
     const T tiny = (sizeof(T) == 4) ? (T)2.4e-7 : (T)4.5e-16;
     // staged radius: in a first pass over lists shared with the parent
     // gradient/force tile, the margin over this tile's largest guessed
@@ -78,7 +99,6 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     const int lt = shared ? uniform(a.parent[t]) : t;  // whose list is staged
     const T hstage = R / eps;
     const T hedge = hstage * ((T)1 - (T)8 * tiny);  // largest h whose support is staged
-    (void)L;
 
     // a guess beyond the staged radius starts at its edge (the radius is
     // capped below half the box)
@@ -92,183 +112,304 @@ __device__ void density_tile(WaveMem<T, CAP, 2>& m, const KArgs<T>& a, int t, Wa
     const int iters0 = iters;
     T S0 = 0, S1 = 0, S2 = 0, Sr = 0, Sdr = 0, Dv = 0, Cx = 0, Cy = 0, Cz = 0;
     int cnt = 0;
-    unsigned long long tested = 0;
+    unsigned long long tested = 0;      // per i-particle
+    unsigned long long tested_all = 0;  // over the tile
     T H = eps * h;
     T H2 = act ? mul_unfused(H, H) : (T)-1;
     T invH = (T)1 / H;
-    auto test = [&](int k, bool ok) {
-        const V4<T> sj = m.s[0][k];
-        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
-    };
-    auto body = [&](int k) {
-        const V4<T> sj = m.s[0][k];
+    // a pair inside the support: sj the staged image position, pj and vj the
+    // partner's pos4 (mass in w) and vel4; vi the particle's own velocity
+    V4<T> vi{};
+    auto body = [&](const V4<T>& sj, const V4<T>& pj, const V4<T>& vj) {
         const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
         const T r2 = dist2_unfused(dx, dy, dz);
-        const V4<T> vj = m.s[1][k];
         const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
-        const T q = r2 * inv_r * invH;
+        const T qq = r2 * inv_r * invH;
         T w, s1, gq;
-        m4_terms(q, H * inv_r, w, s1, gq);
+        m4_terms(qq, H * inv_r, w, s1, gq);
         S0 += w;
         S1 += s1;
-        S2 += m4_q2w2(q);
-        Sr += sj.w * w;
-        Sdr += sj.w * s1;
+        S2 += m4_q2w2(qq);
+        Sr += pj.w * w;
+        Sdr += pj.w * s1;
         const T ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-        const T mg = sj.w * gq;
+        const T mg = pj.w * gq;
         Dv += mg * (ux * dx + uy * dy + uz * dz);
         Cx += mg * (uy * dz - uz * dy);
         Cy += mg * (uz * dx - ux * dz);
         Cz += mg * (ux * dy - uy * dx);
         ++cnt;
     };
+    auto body_k = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        int j = as_int<T>(sj.w);
+        if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid list
+        body(sj, a.pos4[j], a.vel4[j]);
+    };
+    auto test = [&](int k, bool ok) {
+        const V4<T> sj = m.s[0][k];
+        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+    };
     auto sweep = [&](int ns) {
-        pair_loop(m, ns, js, S, test, body);
+        pair_loop(m, ns, js, S, test, body_k);
         tested += (unsigned long long)ns;
     };
     auto zero = [&]() {
         S0 = S1 = S2 = Sr = Sdr = Dv = Cx = Cy = Cz = 0;
         cnt = 0;
     };
-    const T R2 = R * R;
-    int flushes = 0;
-    int ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, R2, flushes, sweep);
-    sweep(ns);
-    const bool cached = flushes == 0;
-    T Rc = R;  // radius of the staged set
-    for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
-        ++iters;
-        const T S0r = stream_sum(S0, q), S1r = stream_sum(S1, q), S2r = stream_sum(S2, q);
-        if (!conv && !pend) {
-            const T G = S0r;
-            if (fabs(G - Tt) <= a.h_tol * Tt) {
+    // One Halley update per lane from the sums of the sweep at h (over the
+    // streams of its i-particle).
+    auto newton = [&](T S0r, T S1r, T S2r) {
+        if (conv || pend) return;
+        const T G = S0r;
+        if (fabs(G - Tt) <= a.h_tol * Tt) {
+            conv = true;
+            return;
+        }
+        // Halley step on F = log(G / target) over log h: G grows about as
+        // h^3, so F is nearly linear in log h, and the third-order step (F'
+        // from h dG/dh = 3 S0 - S1, F'' from the sum of q^2 w''(q) as well)
+        // saves about half a sweep per particle over a Newton step on the
+        // same function
+        const T dl = (T)3 * S0r - S1r;
+        if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
+        const T iG = step_rcp(G);
+        const T F = log1p((G - Tt) * inv_Tt);
+        const T F1 = dl * iG;
+        const T F2 = (S2r - dl) * iG - F1 * F1;
+        const T den = (T)2 * F1 * F1 - F * F2;
+        const T ds = den > (T)0 ? (T)-2 * F * F1 * step_rcp(den) : -F * step_rcp(F1);
+        T hn = h * step_exp(ds);
+        const bool ok = dl > (T)0 && hn > lo_h && hn < hi_h;
+        if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
+        if (!has_upper && hn >= hedge) {
+            // the step leaves the staged set: first try its edge; if the
+            // root lies beyond, the tile gets a fix-up pass
+            if (h < hedge) {
+                h = hedge;
+            } else if (R >= Rcap) {
+                failed = true;
                 conv = true;
             } else {
-                // Halley step on F = log(G / target) over log h: G grows about
-                // as h^3, so F is nearly linear in log h, and the third-order
-                // step (F' from h dG/dh = 3 S0 - S1, F'' from the sum of
-                // q^2 w''(q) as well) saves about half a sweep per particle
-                // over a Newton step on the same function
-                const T dl = (T)3 * S0r - S1r;
-                if (G < Tt) lo_h = h; else { hi_h = h; has_upper = true; }
-                const T F = log1p((G - Tt) / Tt);
-                const T F1 = dl / G;
-                const T F2 = (S2r - dl) / G - F1 * F1;
-                const T den = (T)2 * F1 * F1 - F * F2;
-                const T ds = den > (T)0 ? (T)-2 * F * F1 / den : -F / F1;
-                T hn = h * exp(ds);
-                const bool ok = dl > (T)0 && hn > lo_h && hn < hi_h;
-                if (!ok) hn = has_upper ? (T)0.5 * (lo_h + hi_h) : (T)2 * h;
-                if (!has_upper && hn >= hedge) {
-                    // the step leaves the staged set: first try its edge; if
-                    // the root lies beyond, the tile gets a fix-up pass
-                    if (h < hedge) {
-                        h = hedge;
-                    } else if (R >= Rcap) {
-                        failed = true;
-                        conv = true;
-                    } else {
-                        // next radius from the local h^3 scaling of G (a Newton
-                        // step from below can overshoot far), grown at most 2x
-                        // per pass
-                        pend = true;
-                        const T grow = (T)1.05 * cbrt(Tt / G);
-                        want = h * min((T)2, max((T)1.02, grow));
-                    }
-                } else if (fabs(hn - h) <= tiny * h) {
-                    conv = true;
-                } else {
-                    h = hn;
-                }
+                // next radius from the local h^3 scaling of G (a Newton step
+                // from below can overshoot far), grown at most 2x per pass
+                pend = true;
+                const T grow = (T)1.05 * cbrt(Tt / G);
+                want = h * min((T)2, max((T)1.02, grow));
             }
+        } else if (fabs(hn - h) <= tiny * h) {
+            conv = true;
+        } else {
+            h = hn;
         }
-        if (ballot(!conv && !pend) == 0ull) break;
-        if (sweeps == a.h_max_iter) break;
+    };
+    auto next_h = [&]() {
         H = eps * h;
         H2 = act ? mul_unfused(H, H) : (T)-1;
         invH = (T)1 / H;
-        zero();
-        // the staged set follows the sweep's largest support (the bounding-box
-        // distance never exceeds a lane's distance): a cached set is compacted
-        // in LDS when that support shrank and staged again from the list when
-        // h grew past it (it fit at R, so it fits at any smaller radius); a
-        // set that did not fit is staged again every sweep
-        const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
-        bool restage = !cached;
-        T Rs = Hs < R ? Hs : R;
-        if (cached) {
-            if (Hs > Rc) {
-                Rc = min(R, Hs * (T)1.05);
-                Rs = Rc;
-                restage = true;
-            } else if (Hs < (T)0.9 * Rc) {
-                Rc = Hs * (T)1.05;
-                ns = compact_staged(m, ns, g, Rc * Rc);
+    };
+    const T R2 = R * R;
+    int flushes = 0;
+    int ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, R2, flushes, sweep);
+    bool listed = flushes == 0;
+    // Everything after the staging: lists or re-tested sweeps, the Newton
+    // iteration, the outputs.
+    auto density_sweeps = [&]() {
+        // Neighbour lists, per i-slot in staged order: the staged candidates
+        // within R of the slot's particle (fixed h: within its support, which
+        // may reach R itself).
+        constexpr int NENT = WaveMem<T, CAP, 1>::NENT;
+        const int capl = NENT / c;
+        int lcnt = 0;  // lane l < c: entries of i-slot l
+        if (listed) {
+            const T RL2 = max(R2, H2);
+            for (int b = 0; b < ns; b += WAVE) {
+                const int k = b + lane;
+                const bool have = k < ns;
+                const V4<T> sj = m.s[0][have ? k : 0];
+                for (int l = 0; l < c; ++l) {
+                    const int ll = l * S;  // the slot's first stream
+                    const T px = lane_val(pi.x, ll), py = lane_val(pi.y, ll), pz = lane_val(pi.z, ll);
+                    const bool in = have && dist2_unfused(px - sj.x, py - sj.y, pz - sj.z) <
+                                                lane_val(RL2, ll);
+                    const unsigned long long mk = ballot(in);
+                    const int at = lane_val(lcnt, l) + mbcnt(mk);
+                    if (in && at < capl) m.ent[l * capl + at] = (uint16_t)k;
+                    if (lane == l) lcnt += __popcll(mk);
+                }
+            }
+            listed = ballot(lane < c && lcnt > capl) == 0ull;
+            tested += (unsigned long long)ns;  // per i-particle
+            wave_sync();
+        }
+        constexpr int U = 4;   // list entries of a stream in flight together
+        constexpr int UF = 2;  // the same in the full sweep (two global loads each)
+        if (listed) {
+            // stream js of slot li takes entries js, js + S, ... of li's list
+            const int nl = act ? __shfl(lcnt, q.li, WAVE) : 0;
+            const int nmax = uniform(wave_max(nl));
+            const uint16_t* el = &m.ent[q.li * capl];
+            int evals = 0;
+            for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
+                ++iters;
+                // sweep at h: n and its first two log-h derivatives only
+                T s0 = 0, s1 = 0, s2 = 0;
+                for (int t0 = 0; t0 < nmax; t0 += U * S) {
+                    V4<T> sj[U];
+                    bool ok[U];
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int e = t0 + u * S + js;
+                        ok[u] = e < nl;
+                        sj[u] = m.s[0][ok[u] ? el[e] : 0];
+                    }
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const T r2 = dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y, pi.z - sj[u].z);
+                        if (ok[u] && r2 < H2) {
+                            const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
+                            const T qq = r2 * inv_r * invH;
+                            T w, s1v, gq;
+                            m4_terms(qq, H * inv_r, w, s1v, gq);
+                            s0 += w;
+                            s1 += s1v;
+                            s2 += m4_q2w2(qq);
+                        }
+                    }
+                }
+                evals += nl;
+                newton(group_sum(s0, S), group_sum(s1, S), group_sum(s2, S));
+                if (ballot(!conv && !pend) == 0ull) break;
+                if (sweeps == a.h_max_iter) break;
+                next_h();
+            }
+            vi = a.vel4[i];
+            // the full sums at the final h (partner data from global memory,
+            // the loads of U entries issued together)
+            zero();
+            for (int t0 = 0; t0 < nmax; t0 += UF * S) {
+                V4<T> sj[UF], pj[UF], vj[UF];
+                bool in[UF];
+    #pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    const int e = t0 + u * S + js;
+                    const bool ok = e < nl;
+                    sj[u] = m.s[0][ok ? el[e] : 0];
+                    in[u] = ok && dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y, pi.z - sj[u].z) < H2;
+                }
+    #pragma unroll
+                for (int u = 0; u < UF; ++u) {
+                    int j = in[u] ? as_int<T>(sj[u].w) : 0;
+                    if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid list
+                    pj[u] = a.pos4[j];
+                    vj[u] = a.vel4[j];
+                }
+    #pragma unroll
+                for (int u = 0; u < UF; ++u)
+                    if (in[u]) body(sj[u], pj[u], vj[u]);
+            }
+            evals += nl;
+            // tests: the list pass plus every list evaluation
+            tested_all += (unsigned long long)wave_sum(lead ? evals : 0);
+        } else {
+            vi = a.vel4[i];
+            sweep(ns);
+            const bool cached = flushes == 0;
+            T Rc = R;  // radius of the staged set
+            for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
+                ++iters;
+                newton(group_sum(S0, S), group_sum(S1, S), group_sum(S2, S));
+                if (ballot(!conv && !pend) == 0ull) break;
+                if (sweeps == a.h_max_iter) break;
+                next_h();
+                zero();
+                // the staged set follows the sweep's largest support (the
+                // bounding-box distance never exceeds a lane's distance): a
+                // cached set is compacted in LDS when that support shrank and
+                // staged again from the list when h grew past it (it fit at R, so
+                // it fits at any smaller radius); a set that did not fit is
+                // staged again every sweep
+                const T Hs = wave_max(act ? H : (T)0) * ((T)1 + (T)4 * tiny);
+                bool restage = !cached;
+                T Rs = Hs < R ? Hs : R;
+                if (cached) {
+                    if (Hs > Rc) {
+                        Rc = min(R, Hs * (T)1.05);
+                        Rs = Rc;
+                        restage = true;
+                    } else if (Hs < (T)0.9 * Rc) {
+                        Rc = Hs * (T)1.05;
+                        ns = compact_staged(m, ns, g, Rc * Rc);
+                    }
+                }
+                if (restage) {
+                    int fl = 0;
+                    ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, Rs * Rs, fl, sweep);
+                }
+                sweep(ns);
             }
         }
-        if (restage) {
-            int fl = 0;
-            ns = stage_tile<L_DENS, T, CAP>(m, a, lt, bi, g, Rs * Rs, fl, sweep);
+        S0 = group_sum(S0, S);
+        S1 = group_sum(S1, S);
+        Sr = group_sum(Sr, S);
+        Sdr = group_sum(Sdr, S);
+        Dv = group_sum(Dv, S);
+        Cx = group_sum(Cx, S);
+        Cy = group_sum(Cy, S);
+        Cz = group_sum(Cz, S);
+        cnt = group_sum(cnt, S);
+        const bool last = a.fixup == 2;
+        if (pend && last) { failed = true; pend = false; }
+        if (!conv && !pend && act) failed = true;
+        // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
+        if (lead) {
+            const T Hh = eps * h;
+            const T iH = (T)1 / Hh;
+            const T k3 = cnorm * iH * iH * iH;
+            const T k5 = k3 * iH * iH;
+            const T rho = k3 * Sr;
+            const T drho = -k3 * Sdr / h;
+            const int64_t n = a.n;
+            T* o = a.out;
+            o[0 * n + i] = h;
+            o[1 * n + i] = rho;
+            o[2 * n + i] = drho;
+            o[3 * n + i] = k3 * S0;
+            o[4 * n + i] = -k3 * S1 / h;
+            o[5 * n + i] = -k5 * Dv / rho;
+            o[6 * n + i] = k5 * Cx / rho;
+            o[7 * n + i] = k5 * Cy / rho;
+            o[8 * n + i] = k5 * Cz / rho;
+            o[9 * n + i] = (T)1 / ((T)1 + h * drho / ((T)3 * rho));
+            a.iout[0 * n + i] = cnt - 1;
+            a.iout[1 * n + i] = failed ? -iters : iters;
+            a.hs[i] = pend ? want : h;
         }
-        sweep(ns);
-    }
-    S0 = stream_sum(S0, q);
-    S1 = stream_sum(S1, q);
-    Sr = stream_sum(Sr, q);
-    Sdr = stream_sum(Sdr, q);
-    Dv = stream_sum(Dv, q);
-    Cx = stream_sum(Cx, q);
-    Cy = stream_sum(Cy, q);
-    Cz = stream_sum(Cz, q);
-    cnt = stream_sum(cnt, q);
-    const bool last = a.fixup == 2;
-    if (pend && last) { failed = true; pend = false; }
-    if (!conv && !pend && act) failed = true;
-    // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
-    if (lead) {
-        const T Hh = eps * h;
-        const T iH = (T)1 / Hh;
-        const T k3 = cnorm * iH * iH * iH;
-        const T k5 = k3 * iH * iH;
-        const T rho = k3 * Sr;
-        const T drho = -k3 * Sdr / h;
-        const int64_t n = a.n;
-        T* o = a.out;
-        o[0 * n + i] = h;
-        o[1 * n + i] = rho;
-        o[2 * n + i] = drho;
-        o[3 * n + i] = k3 * S0;
-        o[4 * n + i] = -k3 * S1 / h;
-        o[5 * n + i] = -k5 * Dv / rho;
-        o[6 * n + i] = k5 * Cx / rho;
-        o[7 * n + i] = k5 * Cy / rho;
-        o[8 * n + i] = k5 * Cz / rho;
-        o[9 * n + i] = (T)1 / ((T)1 + h * drho / ((T)3 * rho));
-        a.iout[0 * n + i] = cnt - 1;
-        a.iout[1 * n + i] = failed ? -iters : iters;
-        a.hs[i] = pend ? want : h;
-    }
-    const unsigned long long pmask = ballot(pend);
-    const unsigned long long fmask = ballot(failed && js == 0);
-    const T wmax = wave_max(pend ? want : (T)0);
-    const unsigned long long ins = (unsigned long long)wave_sum(lead ? cnt : 0);
-    if (lane == 0) {
-        if (pmask) {
-            T Rn = eps * wmax * (T)1.0625;
-            if (!(Rn < Rcap)) Rn = Rcap;
-            a.trad[t] = (float)Rn;
-            a.tflag[t] = 1;
-        } else {
-            a.tflag[t] = 0;
+        const unsigned long long pmask = ballot(pend);
+        const unsigned long long fmask = ballot(failed && js == 0);
+        const T wmax = wave_max(pend ? want : (T)0);
+        const unsigned long long ins = (unsigned long long)wave_sum(lead ? cnt : 0);
+        if (lane == 0) {
+            if (pmask) {
+                T Rn = eps * wmax * (T)1.0625;
+                if (!(Rn < Rcap)) Rn = Rcap;
+                a.trad[t] = (float)Rn;
+                a.tflag[t] = 1;
+            } else {
+                a.tflag[t] = 0;
+            }
+            if (fmask) latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
         }
-        if (fmask) latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
-    }
-    ws.restages += pmask ? 1ull : 0ull;
-    ws.tested += tested * (unsigned long long)tl.count;
-    ws.inside += ins;
-    ws.sweeps += (unsigned long long)(iters - iters0);
-    ws.smax = max(ws.smax, (unsigned long long)wave_max(iters));
-    ws.failed += (unsigned long long)__popcll(fmask);
+        ws.restages += pmask ? 1ull : 0ull;
+        ws.tested += tested * (unsigned long long)tl.count + tested_all;
+        ws.inside += ins;
+        ws.sweeps += (unsigned long long)(iters - iters0);
+        ws.smax = max(ws.smax, (unsigned long long)wave_max(iters));
+        ws.failed += (unsigned long long)__popcll(fmask);
+    };
+    density_sweeps();
+    ws.listed += listed ? 1ull : 0ull;
 }
 
 // ------------------------------------------------- gradient and force tile
@@ -394,7 +535,7 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
 
 template <int LK, typename T, int CAP>
 __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, WaveStats& ws) {
-    if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 2>*)wm, a, t, ws);
+    if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 1>*)wm, a, t, ws);
     else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
@@ -431,9 +572,12 @@ static int launch_loop_cap(KArgs<T> a, int mode, int queue_slot, hipStream_t s) 
     return launch_with<LK, T, CAP>(k_loop<LK, T, CAP>, a, mode, queue_slot, s);
 }
 
-// Largest staging capacity <= lds_cap whose workgroup fits in the LDS.
+// Largest staging capacity <= lds_cap whose workgroup fits in the LDS
+// (1024 only for the density loop's fix-up passes).
 template <int LK, typename T>
 static int launch_loop(KArgs<T> a, int mode, int lds_cap, int queue_slot, hipStream_t s) {
+    if constexpr (LK == L_DENS && fits<LK, T, 1024>())
+        if (lds_cap >= 1024) return launch_loop_cap<LK, T, 1024>(a, mode, queue_slot, s);
     if (lds_cap >= 512 && fits<LK, T, 512>()) return launch_loop_cap<LK, T, 512>(a, mode, queue_slot, s);
     if (lds_cap >= 256 && fits<LK, T, 256>()) return launch_loop_cap<LK, T, 256>(a, mode, queue_slot, s);
     static_assert(fits<LK, T, 128>(), "staging buffer does not fit");
@@ -459,8 +603,10 @@ __global__ void k_fix_list(const int32_t* __restrict__ tflag,
     }
 }
 
-// Density: the first pass, then up to three fix-up passes for tiles whose
-// Newton iteration needed a wider task list (the last one latches failures).
+// Density: the first pass, then up to DENS_FIXUPS fix-up passes for tiles
+// whose Newton iteration needed a wider task list (the last pass latches
+// failures).
+constexpr int DENS_FIXUPS = 3;
 template <typename T>
 int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
     const BinPtrs b = density_view(bin);
@@ -485,18 +631,17 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     a.order = b.tmpidx;
     a.ntask = &b.cnt->n_fix;
     a.xcd_split = 0;
-    for (int pass = 1; pass <= 3 && !r; ++pass) {
+    for (int pass = 1; pass <= DENS_FIXUPS && !r; ++pass) {
         launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
         hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
                            (const int32_t*)b.tflag, (const unsigned long long*)b.ntiles, b.cnt,
                            b.tmpidx);
         launch_tasks<T>(b, sc, 0, true, s);
-        a.fixup = pass == 3 ? 2 : 1;
+        a.fixup = pass == DENS_FIXUPS ? 2 : 1;
         timer_begin(sc.timer, 0, s);
         // fix-up tiles are few and their lists long: the largest staging
-        // buffer keeps more of them in LDS across their sweeps
-        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode,
-                                   lds_cap > 512 ? lds_cap : 512, 0, s);
+        // buffer keeps them in LDS across their sweeps
+        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, 1024, 0, s);
         timer_end(sc.timer, 0, s);
     }
     return r;

@@ -17,8 +17,12 @@ struct WaveMem {
     // particle, so the gradient/force kernel's 128 staged particles and
     // lists take 10 KB per wavefront and four wavefronts per SIMD fit LDS
     static constexpr int HL = NV >= 4 ? 16 : LC;
+    static constexpr int NENT = HL * WAVE;
     V4<T> s[NV][CAP];          // staged j-particles
-    uint16_t lst[HL][WAVE];    // per-lane hit lists (staged indices), column per lane
+    union {
+        uint16_t lst[HL][WAVE];  // per-lane hit lists (staged indices), column per lane
+        uint16_t ent[NENT];      // density: per-i neighbour lists (staged indices)
+    };
 };
 
 template <typename T>
@@ -145,22 +149,22 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
     drain();
 }
 
-// Keep, in order and in place, the staged j-particles (two 4-vectors each,
-// the density loop's layout) whose distance to the tile box is below sqrt(R2) (staged positions already carry their periodic
-// image).  Writes never pass the chunk being read, so in place is safe.
-// Returns the new count.
+// Keep, in order and in place, the staged j-particles (one 4-vector each,
+// the density loop's layout) whose distance to the tile box is below
+// sqrt(R2) (staged positions already carry their periodic image).  Writes
+// never pass the chunk being read, so in place is safe.  Returns the new
+// count.
 template <typename T, int CAP>
-__device__ int compact_staged(WaveMem<T, CAP, 2>& m, int ns, const TileGeom& g, T R2) {
+__device__ int compact_staged(WaveMem<T, CAP, 1>& m, int ns, const TileGeom& g, T R2) {
     const int lane = lane_id();
     int out = 0;
     for (int b = 0; b < ns; b += WAVE) {
         const int k = b + lane;
         const bool have = k < ns;
-        V4<T> s0{}, s1{};
+        V4<T> s0{};
         bool keep = false;
         if (have) {
             s0 = m.s[0][k];
-            s1 = m.s[1][k];
             const T x = s0.x, y = s0.y, z = s0.z;
             const T gx = max((T)0, max((T)g.lo[0] - x, x - (T)g.hi[0]));
             const T gy = max((T)0, max((T)g.lo[1] - y, y - (T)g.hi[1]));
@@ -169,15 +173,68 @@ __device__ int compact_staged(WaveMem<T, CAP, 2>& m, int ns, const TileGeom& g, 
         }
         const unsigned long long km = ballot(keep);
         wave_sync();
-        if (keep) {
-            const int o = out + mbcnt(km);
-            m.s[0][o] = s0;
-            m.s[1][o] = s1;
-        }
+        if (keep) m.s[0][out + mbcnt(km)] = s0;
         out += __popcll(km);
         wave_sync();
     }
     return out;
+}
+
+// Sums over aligned groups of S contiguous lanes (S a power of two, the
+// same in every lane), returned in every lane of the group: butterflies on
+// DPP lane permutes within rows of 16 (quad swaps, half-row and row
+// mirrors), a swizzle across the two rows of each half-wavefront, and for
+// S = 64 the two halves read from lanes 0 and 32.  Floating-point addition
+// is commutative, so every lane of a group gets the same bits.
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_v(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_v(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(unsigned)b), hi = dpp_i<CTRL>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL> __device__ __forceinline__ int dpp_v(int v) { return dpp_i<CTRL>(v); }
+constexpr int SWZ_XOR16 = 0x1f | (0x10 << 10);  // ds_swizzle bit mode: lane ^ 16 within 32
+__device__ __forceinline__ int swz16(int v) { return __builtin_amdgcn_ds_swizzle(v, SWZ_XOR16); }
+__device__ __forceinline__ float swz16(float v) { return __int_as_float(swz16(__float_as_int(v))); }
+__device__ __forceinline__ double swz16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = swz16((int)(unsigned)b), hi = swz16((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename V> __device__ __forceinline__ V group_sum(V v, int S) {
+    if (S >= 2) v += dpp_v<0xb1>(v);   // quad_perm 1,0,3,2: lane ^ 1
+    if (S >= 4) v += dpp_v<0x4e>(v);   // quad_perm 2,3,0,1: lane ^ 2
+    if (S >= 8) v += dpp_v<0x141>(v);  // row_half_mirror: the other quad of 8
+    if (S >= 16) v += dpp_v<0x140>(v); // row_mirror: the other 8 of the row
+    if (S >= 32) v += swz16(v);        // the other row of 32
+    if (S >= 64) v = lane_val(v, 0) + lane_val(v, 32);
+    return v;
+}
+
+// Lane mapping of the density loop: a tile of c particles (c <= 64) gets
+// c i-slots of S = the largest power of two <= 64 / c streams each, the
+// streams of a slot on contiguous lanes (lane = S i-slot + stream), so
+// sums over a slot's streams are group_sum(., S).
+struct GroupMap {
+    int c, S, li, js;
+    bool act;
+};
+__device__ __forceinline__ GroupMap group_map(int c) {
+    GroupMap q;
+    q.c = c < 1 ? 1 : (c > WAVE ? WAVE : c);
+    int S = 1;
+    while (2 * S * q.c <= WAVE) S *= 2;
+    q.S = S;
+    const int lane = lane_id();
+    q.act = lane < q.c * S;
+    q.li = q.act ? lane / S : 0;
+    q.js = lane - (lane / S) * S;
+    return q;
 }
 
 // loop kinds: forward loops and the three pair passes of the adjoint
@@ -185,7 +242,7 @@ __device__ int compact_staged(WaveMem<T, CAP, 2>& m, int ns, const TileGeom& g, 
 enum { L_DENS = 0, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
 
 template <int LK> struct LoopNV;
-template <> struct LoopNV<L_DENS> { static constexpr int NV = 2; };
+template <> struct LoopNV<L_DENS> { static constexpr int NV = 1; };
 template <> struct LoopNV<L_FORCE> { static constexpr int NV = 4; };
 template <> struct LoopNV<L_ADJA> { static constexpr int NV = 5; };
 template <> struct LoopNV<L_ADJC> { static constexpr int NV = 2; };
@@ -209,7 +266,7 @@ template <int LK, typename T> struct JData {
 template <int LK, typename T>
 __device__ __forceinline__ void gather_j(const KArgs<T>& a, int j, JData<LK, T>& r) {
     r.p = a.pos4[j];
-    if (LK <= L_ADJA) r.v = a.vel4[j];
+    if (LK == L_FORCE || LK == L_ADJA) r.v = a.vel4[j];
     if (LK == L_FORCE || LK == L_ADJA) r.d = a.dens4[j];
     if (LK >= L_ADJA) r.x = a.aux4[j];
     if (Symmetric<LK>::value) r.h = a.hs[j];
@@ -272,8 +329,9 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int lt, const BoxInfo& bi, c
         if (pass) {
             const V4<T> pa = r.p, va = r.v;
             if (LK == L_DENS) {
-                q0 = V4<T>{xs, ys, zs, pa.w};
-                q1 = V4<T>{va.x, va.y, va.z, (T)0};
+                // image position and the binned index (mass and velocity
+                // are read from global memory for the pairs inside)
+                q0 = V4<T>{xs, ys, zs, int_as<T>(j)};
             } else if (LK == L_FORCE) {
                 const V4<T> da = r.d;
                 const T Hj = mul_unfused(a.eps, r.h);
@@ -415,6 +473,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
 struct WaveStats {
     unsigned long long tested = 0, inside = 0, sweeps = 0, smax = 0, failed = 0, restages = 0;
     unsigned long long inside_g = 0;  // gradient pairs of the joint gradient/force loop
+    unsigned long long listed = 0;    // density tiles swept over neighbour lists
     __device__ void flush(Counters* c, int loop) const {
         if (lane_id() != 0) return;
         if (tested) atomicAdd(&c->pairs_tested[loop], tested);
@@ -427,6 +486,7 @@ struct WaveStats {
         if (smax) atomicMax(&c->newton_max, smax);
         if (failed) atomicAdd(&c->newton_failed, failed);
         if (restages) atomicAdd(&c->restages, restages);
+        if (listed) atomicAdd(&c->dens_listed, listed);
     }
 };
 

@@ -65,7 +65,8 @@ struct Counters {
     unsigned long long n_tiles_d;      // tiles of the density loop
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
     unsigned long long cand_used;      // task-list entries taken by the current build
-    unsigned long long reserved[5];
+    unsigned long long dens_listed;    // density tiles that swept per-particle neighbour lists
+    unsigned long long reserved[4];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };

@@ -92,14 +92,15 @@ class Stats(ctypes.Structure):
                 ("newton_sweeps", ctypes.c_uint64), ("newton_max", ctypes.c_uint32),
                 ("newton_failed", ctypes.c_uint32), ("listed", ctypes.c_uint64),
                 ("restages", ctypes.c_uint64), ("n_tiles_dens", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 5)]
+                ("dens_listed", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
 
     def as_dict(self) -> Dict:
         return {"status": self.status, "n_tiles": self.n_tiles,
                 "pairs_tested": list(self.pairs_tested), "pairs_inside": list(self.pairs_inside),
                 "newton_sweeps": self.newton_sweeps, "newton_max": self.newton_max,
                 "newton_failed": self.newton_failed, "listed": self.listed,
-                "restages": self.restages, "n_tiles_dens": self.n_tiles_dens}
+                "restages": self.restages, "n_tiles_dens": self.n_tiles_dens,
+                "dens_listed": self.dens_listed}
 
 
 _vp = ctypes.c_void_p
