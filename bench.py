@@ -11,11 +11,15 @@ stream), whole steps between synchronisations.
 
 Metric: pair interactions per second of the density and force loops
 (useful pairs: r < H_i for density, r < max(H_i, H_j) for force) over the
-whole step time.  Reported alongside: per-loop rates, the fraction of the
+whole step time.  Reported alongside: per-loop rates and fractions of the
 FP32 vector peak reached by the arithmetic of the useful pairs, the same
-step with one kernel launch per tile task (the per-task offload baseline),
-the roofline entry of the dominant kernel and the FP64 oracle on the host
-cores.
+step with a flat launch (static schedule) and with one kernel launch per
+tile task (the per-task offload baseline), a warm-started step (the previous
+h as the guess), the autotuner's choice, the roofline entry of the dominant
+kernel (with FP32 VALU counter figures and HBM traffic from the committed
+rocprofv3 summaries while the kernel sources match them), the many-boxes set
+(256 boxes in one launch per loop), the differentiation set (forward and
+adjoint) and the FP64 oracle on the host cores.
 """
 import argparse
 import json
@@ -30,8 +34,8 @@ sys.path.insert(0, ROOT)
 
 # FLOPs per useful pair, counted on the arithmetic each loop performs for a
 # pair inside the support (FMA = 2, add/mul/min/max = 1, sqrt/rsqrt/rcp = 1).
-F_DENS = 59.0     # full density sums (n, dn/dh, d2n/dlogh2, rho, drho/dh, div v, curl v)
-F_NEWTON = 29.0   # each additional Newton sweep (n and its first two log-h derivatives)
+F_LIGHT = 36.0    # one Halley sweep over a particle's list: n, dn/dlogh, sum q^2 w''
+F_FULL = 66.0     # the final full density sums (n, dn/dh, rho, drho/dh, div v, curl v)
 F_GRAD = 33.0     # the gradient loop on its own
 F_FORCE = 67.0
 F_GRAD_JOINT = 17.0  # a gradient pair inside the joint gradient/force body
@@ -48,16 +52,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clustered_128cubed.json")
 
 
 def sources_digest():
-    """sha256 over the library's kernel sources (csrc/*.hip, *.h), sorted by name."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2505_14538_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    """sha256 over the library's kernel sources (the digest the committed
+    counter summaries carry)."""
+    from paper_2505_14538_amd.profsum import sources_digest as digest
+    return digest()
 
 
 def measured_traffic(kernel):
@@ -127,6 +125,111 @@ def copy_probe(nbytes):
     log("copy probe: 5 copies of %d bytes" % nbytes)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "valu_clustered_128cubed.json")
+
+
+def measured_counters(kernel):
+    """FP32 VALU counter figures per dispatch of `kernel` from the committed
+    rocprofv3 summary (SQ_INSTS_VALU_FLOPS_FP32 and the instruction counts),
+    or None when the kernel sources changed since they were taken."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    return t.get("kernels", {}).get(kernel)
+
+
+def timed_steps(plan, dp, steps, warmup):
+    """Mean ms of `steps` graph-replayed steps after `warmup` untimed ones."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = None
+    for _ in range(warmup):
+        out = plan.step(dp)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        out = plan.step(dp)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, out
+
+
+def step_flops(P_d, P_f, sweeps):
+    """Useful-pair FLOPs of one step per loop: density (Halley sweeps over the
+    lists plus the final full sums) and the joint gradient/force loop."""
+    return {"density": P_d * (F_FULL + sweeps * F_LIGHT),
+            "gradient+force": P_d * F_GRAD_JOINT + P_f * F_FORCE}
+
+
+def pairs_of(d, f):
+    import torch
+    return (float(d["nngb"].to(torch.int64).sum().item()),
+            float(f["nint"].to(torch.int64).sum().item()))
+
+
+def many_boxes_leg(S, W, args):
+    """The many-boxes set (256 independent periodic boxes, ~4.7M particles):
+    one graph-replayed step of all boxes, every loop one persistent launch
+    over the tiles of all boxes."""
+    log("many-boxes workload")
+    parts = W.many_boxes()
+    dp = S.to_device(parts)
+    plan = S.Plan()
+    ms, (d, g, f) = timed_steps(plan, dp, args.steps, args.warmup)
+    st = plan.stats()
+    if st["code"] != 0:
+        raise SystemExit("many boxes: device status %s" % st)
+    P_d, P_f = pairs_of(d, f)
+    sweeps = st["newton_sweeps"] / max(1, st["n_tiles_dens"])
+    fl = step_flops(P_d, P_f, sweeps)
+    log("many boxes: %.3f ms per step" % ms)
+    return {"workload": "256 periodic unit boxes, N_b log-uniform in [2048, 65536] rounded to "
+                        "cubes, jittered lattices, FP32", "n": parts.n, "n_box": parts.n_box,
+            "ms_per_step": ms, "value": (P_d + P_f) / (ms * 1e-3),
+            "unit": "pair interactions/s",
+            "frac_fp32_peak": sum(fl.values()) / (ms * 1e-3) / PEAK_FP32,
+            "newton_sweeps_per_tile": sweeps}
+
+
+def diff_leg(S, W, args):
+    """The differentiation set (64^3 jittered lattice): the FP32 forward
+    (bin, density with Newton, force) and the hand-written adjoint."""
+    import torch
+    log("differentiation workload")
+    parts, w, c = W.diff()
+    dp = S.to_device(parts)
+    plan = S.Plan()
+    gw = torch.as_tensor(w, device="cuda")
+    gc = torch.as_tensor(c, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd, bwd = [], []
+    for rep in range(args.warmup + args.steps):
+        ev[0].record()
+        plan.bin(dp)
+        d = plan.density(dp)
+        f = plan.force(dp, d)
+        ev[1].record()
+        plan.bin(dp)
+        plan.force_backward(dp, d, gw[:, 0].contiguous(), gw[:, 1].contiguous(),
+                            gw[:, 2].contiguous(), gc)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if rep >= args.warmup:
+            fwd.append(ev[0].elapsed_time(ev[1]))
+            bwd.append(ev[1].elapsed_time(ev[2]))
+    st = plan.stats()
+    if st["code"] != 0:
+        raise SystemExit("differentiation: device status %s" % st)
+    log("diff: forward %.3f ms, adjoint %.3f ms" % (np.median(fwd), np.median(bwd)))
+    return {"workload": "64^3 jittered lattice, v ~ N(0, 0.1), u ~ U(0.5, 1.5), FP32; "
+                        "loss sum w.a + c du/dt", "n": parts.n,
+            "forward_ms": float(np.median(fwd)), "adjoint_ms": float(np.median(bwd))}
+
+
 def run(args):
     import torch
     from paper_2505_14538_amd import swsph as S
@@ -137,44 +240,30 @@ def run(args):
     log("generating clustered workload")
     parts = W.clustered()
     dp = S.to_device(parts)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # the batched path: the whole step captured in a HIP graph by the library
-    # (bin + three persistent loop launches), replayed each step.  The plan's
+    # (bin + persistent loop launches), replayed each step, with the plan's
     # default options (tile sizes, LDS capacities, task order, search leaf
-    # size) are the library autotuner's choice on this workload; --autotune
-    # runs the autotuner first (untimed, like a warm-up)
+    # size); the autotune leg below reports the autotuner's own choice
     plan = S.Plan()
     defaults = plan.tuning()
-    tuning = {}
-    if args.autotune:
-        tuning = plan.autotune(dp)
-        log("autotuned: %s" % tuning)
-    for _ in range(args.warmup):
-        d, g, f = plan.step(dp)
-    torch.cuda.synchronize()
-    log("warm-up done")
-    ev0.record()
-    for _ in range(args.steps):
-        d, g, f = plan.step(dp)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_step = ev0.elapsed_time(ev1) / 1e3 / args.steps
+    ms, (d, g, f) = timed_steps(plan, dp, args.steps, args.warmup)
+    t_step = ms * 1e-3
+    log("warm-up and timed steps done")
     st = plan.stats()
     if st["code"] != 0:
         raise SystemExit("device status %s" % st)
-    nngb = d["nngb"].to(torch.int64).sum().item()
-    nint = f["nint"].to(torch.int64).sum().item()
-    P_d, P_f, P_g = float(nngb), float(nint), float(nngb)
+    P_d, P_f = pairs_of(d, f)
+    P_g = P_d
     sweeps = st["newton_sweeps"] / max(1, st["n_tiles_dens"])   # counters cover the last step
     value = (P_d + P_f) / t_step
-    flops = P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON) + P_g * F_GRAD_JOINT + P_f * F_FORCE
-    frac_peak = flops / t_step / PEAK_FP32
+    fl = step_flops(P_d, P_f, sweeps)
+    frac_peak = sum(fl.values()) / t_step / PEAK_FP32
     log("step %.3f ms  P_d %.3e P_f %.3e  sweeps/tile %.2f" % (t_step * 1e3, P_d, P_f, sweeps))
 
     # per-launch duration of the loop kernels: the same step run eagerly with
     # HIP events recorded by the library on this stream around every launch
-    tp = S.Plan(flags=S.TIMING, **tuning)
+    tp = S.Plan(flags=S.TIMING)
     tp.step(dp)
     torch.cuda.synchronize()
     tp.reset_timers()
@@ -183,32 +272,77 @@ def run(args):
     kt = tp.kernel_times()
     log("kernel ms per launch: " + ", ".join("%s %.3f (%d)" % (k, v["ms"], v["launches"])
                                              for k, v in kt.items()))
+    loop_pairs = {"density": P_d, "gradient+force": P_g + P_f}
+    loop = {}
+    for k in ("density", "gradient+force"):
+        if k not in kt:
+            continue
+        per_step_ms = kt[k]["ms"] * kt[k]["launches"] / args.steps
+        loop[k] = {"pairs_per_s": loop_pairs[k] / (per_step_ms * 1e-3),
+                   "kernel_ms_per_step": per_step_ms,
+                   "kernel_ms_per_launch": kt[k]["ms"],
+                   "launches_per_step": kt[k]["launches"] / args.steps,
+                   "flops_per_step": fl[k],
+                   "frac_fp32_peak": fl[k] / (per_step_ms * 1e-3) / PEAK_FP32}
+    tests = {"density": st["pairs_tested"][0] / max(1, st["pairs_inside"][0]),
+             "gradient+force": st["pairs_tested"][2] / max(1, st["pairs_inside"][2])}
+    for k in loop:
+        loop[k]["candidate_tests_per_useful_pair"] = tests[k]
+
+    legs = not args.only_step
+    flat_ms = warm_ms = warm_sweeps = tuned = tuned_ms = None
+    if legs:
+        # the same step with a flat launch (one launch per loop, tasks dealt
+        # round-robin: a static schedule, no queue)
+        flat_ms, _ = timed_steps(S.Plan(flags=S.FLAT_LAUNCH), dp, args.steps, 1)
+        log("flat launch step %.3f ms" % flat_ms)
+
+        # warm start: the converged h of the previous step as the guess
+        hprev = d["h"].clone()
+        dpw = S.to_device(parts)
+        dpw.h = hprev
+        pw = S.Plan()
+        warm_ms, _ = timed_steps(pw, dpw, args.steps, args.warmup)
+        stw = pw.stats()
+        warm_sweeps = stw["newton_sweeps"] / max(1, stw["n_tiles_dens"])
+        log("warm-start step %.3f ms, sweeps/tile %.2f" % (warm_ms, warm_sweeps))
+
+        # the library's autotuner on this workload (untimed search), then the
+        # step with its choice
+        pa = S.Plan()
+        tuned = pa.autotune(dp)
+        tuned_ms, _ = timed_steps(pa, dp, args.steps, 1)
+        log("autotuned %s: %.3f ms" % (tuned, tuned_ms))
 
     t_pt = value_pt = None
-    if not args.no_per_task:
-        t_pt = per_task_step(S, dp, st["n_tiles"], tuning)
+    if legs and not args.no_per_task:
+        t_pt = per_task_step(S, dp, st["n_tiles"], {})
         value_pt = (P_d + P_f) / t_pt
         log("per-task launch step %.1f ms" % (t_pt * 1e3))
-
 
     # roofline of the dominant kernel (largest share of the step); the
     # density kernel runs once plus its fix-up passes per step, so its
     # algorithmic FLOPs per launch are the step's density FLOPs divided by
     # the launches per step
-    dom = max(kt, key=lambda k: kt[k]["ms"] * kt[k]["launches"])
-    k_ms = kt[dom]["ms"]
-    per_step = kt[dom]["launches"] / args.steps
-    per_launch_flops = {"density": P_d * (F_DENS + max(0.0, sweeps - 1) * F_NEWTON),
-                        "gradient+force": P_g * F_GRAD_JOINT + P_f * F_FORCE}[dom] / per_step
+    dom = max(loop, key=lambda k: loop[k]["kernel_ms_per_step"])
+    k_ms = loop[dom]["kernel_ms_per_launch"]
+    per_launch_flops = fl[dom] / loop[dom]["launches_per_step"]
     achieved = per_launch_flops / (k_ms * 1e-3) / 1e12
+    kname = {"density": "k_loop<0", "gradient+force": "k_loop<2"}[dom]
+    cnt = measured_counters(kname)
+    counters = None
+    if cnt is not None:
+        counters = {"valu_fp32_flops_per_launch": cnt["valu_flops_fp32"],
+                    "valu_fp32_tflops": cnt["valu_flops_fp32"] / (k_ms * 1e-3) / 1e12,
+                    "useful_share": per_launch_flops / cnt["valu_flops_fp32"],
+                    "valu_insts_per_useful_pair":
+                        cnt["valu_insts"] * loop[dom]["launches_per_step"] / loop_pairs[dom],
+                    "source": os.path.relpath(COUNTERS_FILE, ROOT)}
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32 / 1e12),
-                # counters were taken with the default options
-                "traffic": measured_traffic({"density": "k_loop<0",
-                                             "gradient+force": "k_loop<2"}[dom])
-                           if not tuning or tuning == defaults else None,
+                "traffic": measured_traffic(kname),
                 "kernel": "k_loop<%s> (loop kernel of the %s loop)" % (dom, dom),
-                "kernel_ms": k_ms}
+                "kernel_ms": k_ms, "counters": counters}
     res = {
         "metric": "pair interactions/s (density+force), % FP32 peak; batched vs per-task launch",
         "value": value,
@@ -225,23 +359,27 @@ def run(args):
         "config": {"workload": "clustered 128^3: 2,097,152 particles, lognormal field "
                                "sigma_ln=1.5 on 64^3 grid, periodic unit box, FP32",
                    "n": parts.n, "loops": "bin+density(Newton)+gradient+force",
-                   "tuning": tuning or "defaults"},
+                   "tuning": defaults},
         "pairs": {"density": P_d, "gradient": P_g, "force": P_f},
-        # per loop: useful pairs over the loop kernels' time per step (the
-        # density loop runs its kernel once plus its fix-up passes)
-        # (the gradient and force loops run in one kernel: their pairs together)
-        "rates": {k: {"pairs_per_s": {"density": P_d, "gradient+force": P_g + P_f}[k] /
-                      (kt[k]["ms"] * kt[k]["launches"] / args.steps * 1e-3),
-                      "kernel_ms_per_launch": kt[k]["ms"],
-                      "launches_per_step": kt[k]["launches"] / args.steps}
-                  for k in kt if k in ("density", "gradient+force")},
         "frac_fp32_peak": frac_peak,
         "newton_sweeps_per_tile": sweeps,
-        "per_task_launch": None if args.no_per_task else {
+        "loops": loop,
+        "flat_launch": None if not legs else {
+            "ms_per_step": flat_ms, "value": (P_d + P_f) / (flat_ms * 1e-3),
+            "batched_speedup": flat_ms * 1e-3 / t_step},
+        "per_task_launch": None if t_pt is None else {
             "value": value_pt, "ms_per_step": t_pt * 1e3, "batched_speedup": t_pt / t_step},
+        "warm_start": None if not legs else {
+            "ms_per_step": warm_ms, "value": (P_d + P_f) / (warm_ms * 1e-3),
+            "newton_sweeps_per_tile": warm_sweeps},
+        "autotune": None if not legs else {
+            "choice": tuned, "matches_defaults": tuned == defaults, "ms_per_step": tuned_ms},
         "roofline": roofline,
     }
-    if not args.no_cpu:
+    if legs and not args.no_extra:
+        res["many_boxes"] = many_boxes_leg(S, W, args)
+        res["differentiation"] = diff_leg(S, W, args)
+    if legs and not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(parts)
     print(json.dumps(res), flush=True)
@@ -253,8 +391,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the library's autotuner on the workload before timing")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the many-boxes and differentiation legs")
+    ap.add_argument("--only-step", action="store_true",
+                    help="only the batched and the timed eager step (profiler runs)")
     ap.add_argument("--no-per-task", action="store_true",
                     help="skip the per-task launch baseline (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
