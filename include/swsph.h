@@ -243,6 +243,59 @@ int swsph_force_backward(swsph_plan* plan, const swsph_particles* p,
                          const swsph_density_out* d, const swsph_force_grad* g,
                          swsph_input_grad* gi, void* ws, void* stream);
 
+/* Time-dependent dissipation switches (Sec. 2.1.3 Eq. 12-16, Sec. 2.1.4
+ * Eq. 19-24), the readings of the printed equations: alpha_loc =
+ * alpha_V,max S / (v_sig^2 + S) with S = H^2 max(0, -(div v - div v_prev)/dt)
+ * (Eq. 13-15, v_sig of the previous gradient loop); alpha_V jumps up to
+ * alpha_loc or relaxes towards it as exp(-l c dt / H) (Eq. 12), floored at
+ * alpha_V,min; the Balsara factor B = |div v| / (|div v| + |curl v| +
+ * bal_eps c / H) (Eq. 16's B); alpha_ij = (alpha_V,i + alpha_V,j)/2
+ * (B_i + B_j)/2 replaces the constant alpha of Eq. 9; alpha_c takes one
+ * explicit step of d alpha_c/dt = beta_c H lap u / sqrt(u) - (alpha_c -
+ * alpha_c,min) v_sig / H (Eq. 21) and is clamped to [alpha_c,min,
+ * alpha_c,max (1 - alpha_V,ngb / alpha_V,max)] (Eq. 23-24, alpha_V,ngb the
+ * largest alpha_V over the particle's support); the force loop adds the
+ * conduction sum_j alpha_c,ij v_c,ij m_j (u_i - u_j) (f_i dW/dr(h_i) +
+ * f_j dW/dr(h_j)) / (rho_i + rho_j) to du/dt (Eq. 19), with alpha_c,ij =
+ * (P_i alpha_c,i + P_j alpha_c,j) / (P_i + P_j) (Eq. 20) and v_c,ij =
+ * |v_ij . r_hat| + sqrt(2 |P_i - P_j| / (rho_i + rho_j)) (Eq. 22). */
+typedef struct swsph_switch_params {
+    double dt;           /* time step of the switch update (> 0) */
+    double av_max;       /* alpha_V,max (> 0) */
+    double av_min;       /* alpha_V,min (>= 0) */
+    double ell;          /* decay length l of Eq. 12 (>= 0; the paper uses 0.05) */
+    double beta_c;       /* beta_c of Eq. 21 (>= 0) */
+    double ac_min;       /* alpha_c,min (>= 0) */
+    double ac_max;       /* alpha_c,max (>= alpha_c,min) */
+    double bal_eps;      /* Balsara softening in units of c / H (>= 0) */
+} swsph_switch_params;
+
+/* Per-particle switch state (device arrays of the plan's dtype, caller's
+ * order).  alpha_v and alpha_c are read (time t) and overwritten (t + dt);
+ * div_v_prev and v_sig_prev are the previous step's density and gradient
+ * outputs; balsara and alpha_v_ngb, when not NULL, receive B and the
+ * largest alpha_V over each support. */
+typedef struct swsph_switch_state {
+    void* alpha_v;
+    void* alpha_c;
+    const void* div_v_prev;
+    const void* v_sig_prev;
+    void* balsara;
+    void* alpha_v_ngb;
+} swsph_switch_state;
+
+/* Gradient and force loops with the switches at the density results d
+ * (which must include div_v and curl_x/y/z): the viscosity switch, the
+ * gradient loop (v_sig, lap u and alpha_V,ngb), the conduction switch, then
+ * the force loop with alpha_ij and conduction.  Needs swsph_bin and
+ * swsph_density on the same particles; go and fo are written like
+ * swsph_gradient / swsph_force (nint optional).  Arguments are checked on
+ * the host (SWSPH_E_ARG). */
+int swsph_gradient_force_sw(swsph_plan* plan, const swsph_particles* p,
+                            const swsph_density_out* d, const swsph_switch_params* sp,
+                            swsph_switch_state* st, swsph_gradient_out* go,
+                            swsph_force_out* fo, void* ws, void* stream);
+
 /* One whole step: bin, density, gradient and force (go / fo may be NULL to
  * skip that loop).  The step is captured once into a HIP graph (on a
  * stream the plan creates) and replayed on `stream` while the particle,
@@ -290,8 +343,9 @@ int swsph_autotune(swsph_plan* plan, const swsph_particles* p, void* ws, void* s
 
 /* Per-launch duration of the loop kernels, from HIP events the library
  * records on the call's stream around each loop-kernel launch when the plan
- * has SWSPH_TIMING (index 0 density, 2 the joint gradient and force loop,
- * 3 backward pair passes; index 1 is no longer used and stays 0).  ms[k] = mean milliseconds per launch, launches[k] = launches
+ * has SWSPH_TIMING (index 0 density, 1 the gradient loop with switches, 2 the
+ * force loop (the joint gradient and force loop, or the force loop with
+ * switches), 3 backward pair passes).  ms[k] = mean milliseconds per launch, launches[k] = launches
  * timed since the last reset.  Synchronises the stream.  Without
  * SWSPH_TIMING every entry is 0. */
 int swsph_kernel_times(swsph_plan* plan, double ms[4], uint64_t launches[4], void* stream);

@@ -155,7 +155,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.tflag = take(4 * (uint64_t)toff);
     l.d_out = take(10 * T * N);
     l.d_int = take(2 * 4 * N);
-    l.g_out = take(2 * T * N);
+    l.g_out = take(3 * T * N);
     l.f_out = take(4 * T * N);
     l.f_int = take(4 * N);
     l.adj = take(32 * T * (uint64_t)adj_stride(n));
@@ -603,6 +603,65 @@ int swsph_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_ou
                 swsph_force_out* o, void* ws, void* stream) {
     if (pl && !o) return fail(SWSPH_E_ARG, "force output is NULL");
     return gf_checked(pl, p, d, nullptr, o, ws, stream);
+}
+
+int swsph_gradient_force_sw(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                            const swsph_switch_params* sp, swsph_switch_state* st,
+                            swsph_gradient_out* go, swsph_force_out* fo, void* ws,
+                            void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f || !d->div_v || !d->curl_x ||
+                            !d->curl_y || !d->curl_z)))
+        return fail(SWSPH_E_ARG, "switches need density h, rho, f, div_v and curl_x/y/z");
+    if (!sp) return fail(SWSPH_E_ARG, "switch parameters are NULL");
+    if (!(sp->dt > 0) || !(sp->av_max > 0) || !(sp->av_min >= 0) || !(sp->ell >= 0) ||
+        !(sp->beta_c >= 0) || !(sp->ac_min >= 0) || !(sp->ac_max >= sp->ac_min) ||
+        !(sp->bal_eps >= 0))
+        return fail(SWSPH_E_ARG, "switch parameters out of range (dt > 0, av_max > 0, "
+                                 "av_min, ell, beta_c, ac_min, bal_eps >= 0, ac_max >= ac_min)");
+    if (!st || (p->n > 0 && (!st->alpha_v || !st->alpha_c || !st->div_v_prev || !st->v_sig_prev)))
+        return fail(SWSPH_E_ARG, "switch state needs alpha_v, alpha_c, div_v_prev, v_sig_prev");
+    if (!go || !fo || (p->n > 0 && (!go->v_sig || !go->lap_u || !fo->ax || !fo->ay || !fo->az ||
+                                     !fo->dudt)))
+        return fail(SWSPH_E_ARG, "gradient and force outputs are required");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int mode = mode_of(pl);
+    const int64_t n = b.n;
+    const SwitchConsts sw{sp->dt, sp->av_max, sp->av_min, sp->ell, sp->beta_c, sp->ac_min,
+                          sp->ac_max, sp->bal_eps};
+    const bool f64 = pl->cfg.dtype == SWSPH_F64;
+    if (f64) {
+        launch_prep_dens<double>(b, sc, d, s);
+        launch_gf_tasks<double>(b, sc, s);
+        r = launch_switch_loops<double>(b, sc, sw, d, st, mode, pl->lds_cap, s);
+    } else {
+        launch_prep_dens<float>(b, sc, d, s);
+        launch_gf_tasks<float>(b, sc, s);
+        r = launch_switch_loops<float>(b, sc, sw, d, st, mode, pl->lds_cap, s);
+    }
+    if (r) return fail(SWSPH_E_HIP, "switch loop launch failed");
+    const size_t tsz = f64 ? 8 : 4;
+    UnsortSet u{};
+    u.in[0] = b.g_out;
+    u.out[0] = go->v_sig;
+    u.in[1] = (char*)b.g_out + tsz * n;
+    u.out[1] = go->lap_u;
+    void* dst[4] = {fo->ax, fo->ay, fo->az, fo->dudt};
+    for (int k = 0; k < 4; ++k) {
+        u.in[2 + k] = (char*)b.f_out + tsz * k * n;
+        u.out[2 + k] = dst[k];
+    }
+    u.k = 6;
+    if (f64) launch_unsort_multi<double>(n, b.rank, u, s);
+    else launch_unsort_multi<float>(n, b.rank, u, s);
+    if (fo->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, fo->nint, s);
+    return hip_check(hipGetLastError(), "gradient+force with switches");
 }
 
 int swsph_kernel_times(swsph_plan* pl, double ms[4], uint64_t launches[4], void* stream) {

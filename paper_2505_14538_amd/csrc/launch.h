@@ -120,6 +120,15 @@ void launch_gf_tasks(const BinPtrs& b, const Scheme& sc, hipStream_t s);
 // The gradient and the force loop in one kernel (binned outputs g_out, f_out).
 template <typename T>
 int launch_force(const BinPtrs& b, const Scheme& sc, int mode, int lds_cap, hipStream_t s);
+// Constants of the time-dependent switches (swsph_switch_params).
+struct SwitchConsts {
+    double dt, av_max, av_min, ell, beta_c, ac_min, ac_max, bal_eps;
+};
+// The gradient and force loops with the switches (lists from launch_gf_tasks).
+template <typename T>
+int launch_switch_loops(const BinPtrs& b, const Scheme& sc, const SwitchConsts& sw,
+                        const swsph_density_out* d, const swsph_switch_state* st, int mode,
+                        int lds_cap, hipStream_t s);
 template <typename T>
 int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* g,
                     const swsph_density_out* d, int lds_cap, hipStream_t s);

@@ -531,20 +531,216 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
     ws.tested += tested * (unsigned long long)tl.count;
 }
 
+// ------------------------------------------- loops with time-dependent switches
+// The SPHENIX-type switches (Sec. 2.1.3 Eq. 12-16, Sec. 2.1.4 Eq. 19-24) need
+// the gradient loop's results before the force loop: the viscosity
+// coefficient alpha_V is updated after the density loop, the gradient loop
+// gives v_sig, the Laplacian of u and the largest alpha_V over each
+// particle's support, the conduction coefficient alpha_c is updated from
+// them, and only then runs the force loop with alpha_ij = mean(alpha_V)
+// mean(B) and artificial conduction.  So the two loops run as two kernels
+// over the same (force) task lists.  aux4 holds (alpha_V, B, alpha_c, 0) per
+// binned particle.
+
+// Gradient loop (r < H_i): v_sig, the Laplacian of u, and max alpha_V over
+// the support, the particle itself and coincident neighbours included.
+template <typename T, int CAP>
+__device__ void grad_sw_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t, WaveStats& ws) {
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
+    if (tl.count <= 0) return;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
+    const bool lead = act && js == 0;
+    const int i = tl.begin + (act ? q.li : 0);
+    const BoxInfo bi = a.boxtab[tl.box];
+    const V4<T> pi = a.pos4[i];
+    const V4<T> vi = a.vel4[i];
+    const V4<T> di = a.dens4[i];  // (rho, f, c, A)
+    const T h = a.hs[i];
+    const TileGeom g = geom_of(tl);
+    const T H = mul_unfused(a.eps, h);
+    const T H2 = act ? mul_unfused(H, H) : (T)-1;
+    const T invH = (T)1 / H;
+    const T R = (T)a.trad[t];
+    const T cn = (T)(8.0 / PI_D);
+    const T ci = di.z, ui = vi.w;
+    T vsig = (T)2 * ci, lap = 0, avmax = a.aux4[i].x;
+    int inside = 0;
+    unsigned long long tested = 0;
+    auto test = [&](int k, bool ok) {
+        const V4<T> sj = m.s[0][k];
+        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+    };
+    auto body = [&](int k) {
+        const V4<T> sj = m.s[0][k];   // (x, y, z, m_j / rho_j)
+        const V4<T> vj = m.s[1][k];   // (v, c_j)
+        const V4<T> wj = m.s[2][k];   // (u_j, alpha_V,j)
+        avmax = wj.y > avmax ? wj.y : avmax;
+        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        if (r2 > (T)0) {
+            const T inv_r = fast_rsqrt(r2);
+            const T r = r2 * inv_r;
+            const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+            const T vdote = vr * inv_r;
+            const T mu = vdote < (T)0 ? vdote : (T)0;
+            const T vs = ci + vj.w - a.beta * mu;
+            vsig = vs > vsig ? vs : vsig;
+            const T qq = r * invH;
+            const T t1 = (T)1 - qq;
+            const T gq = qq < (T)0.5 ? (T)18 * qq - (T)12 : (T)-6 * t1 * t1 * (H * inv_r);
+            lap += sj.w * (ui - wj.x) * gq;
+            ++inside;
+        }
+    };
+    auto sweep = [&](int ns) {
+        pair_loop(m, ns, js, S, test, body);
+        tested += (unsigned long long)ns;
+    };
+    int flushes = 0;
+    const int ns = stage_tile<L_GSW, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
+    sweep(ns);
+    vsig = stream_max(vsig, q);
+    avmax = stream_max(avmax, q);
+    lap = stream_sum(lap, q);
+    inside = stream_sum(inside, q);
+    if (lead) {
+        const T k5 = cn * invH * invH * invH * invH * invH;
+        a.gout[0 * a.n + i] = vsig;
+        a.gout[1 * a.n + i] = (T)2 * k5 * lap;
+        a.gout[2 * a.n + i] = avmax;
+    }
+    ws.inside += (unsigned long long)wave_sum(lead ? inside : 0);
+    ws.tested += tested * (unsigned long long)tl.count;
+}
+
+// Force loop with alpha_ij = (alpha_V,i + alpha_V,j)/2 (B_i + B_j)/2 in the
+// viscosity (Eq. 9, 16) and artificial conduction in du/dt (Eq. 19-20, 22).
+template <typename T, int CAP>
+__device__ void force_sw_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t, WaveStats& ws) {
+    Tile tl = a.tiles[t];
+    tl.begin = uniform(tl.begin);
+    tl.count = uniform(tl.count);
+    tl.box = uniform(tl.box);
+    if (tl.count <= 0) return;
+    const LaneMap q = lane_map(tl.count);
+    const int js = q.js, S = q.S;
+    const bool act = q.used();
+    const bool lead = act && js == 0;
+    const int i = tl.begin + (act ? q.li : 0);
+    const BoxInfo bi = a.boxtab[tl.box];
+    const V4<T> pi = a.pos4[i];
+    const V4<T> vi = a.vel4[i];
+    const V4<T> di = a.dens4[i];  // (rho, f, c, A)
+    const V4<T> swi = a.aux4[i];  // (alpha_V, B, alpha_c, 0)
+    const T h = a.hs[i];
+    const TileGeom g = geom_of(tl);
+    const T eps = a.eps;
+    const T H = mul_unfused(eps, h);
+    const T H2 = act ? mul_unfused(H, H) : (T)-1;
+    const T invH = (T)1 / H;
+    const T R = (T)a.trad[t];
+    const T cn = (T)(8.0 / PI_D);
+    const T kgi = cn * invH * invH * invH * invH;
+    const T rhoi = di.x, fi = di.y, ci = di.z, Ai = di.w, ui = vi.w;
+    const T Pi = (a.gamma - (T)1) * rhoi * ui;
+    const bool visc = (a.flags & SWSPH_NO_VISC) == 0;
+    T ax = 0, ay = 0, az = 0, du = 0;
+    unsigned long long tested = 0;
+    int hits = 0;
+    auto test = [&](int k, bool ok) {
+        const V4<T> sj = m.s[0][k];
+        const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
+        const bool in = ok && act && r2 < max(H2, sj.w);
+        hits += in ? 1 : 0;
+        return in && r2 > (T)0;
+    };
+    auto body = [&](int k) {
+        const V4<T> sj = m.s[0][k];
+        const T dx = pi.x - sj.x, dy = pi.y - sj.y, dz = pi.z - sj.z;
+        const T r2 = dist2_unfused(dx, dy, dz);
+        const V4<T> vj = m.s[1][k];  // (v, c_j)
+        const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
+        const V4<T> ej = m.s[3][k];  // (rho_j, P_j, u_j, 0)
+        const V4<T> wj = m.s[4][k];  // (alpha_V,j, B_j, alpha_c,j, 0)
+        const T rhoj = ej.x;
+        const T inv_r = fast_rsqrt(r2);
+        const T r = r2 * inv_r;
+        const T gi = r2 < H2 ? kgi * m4_dw(r * invH) : (T)0;
+        const T ihj = cj.w;
+        const T gj = r2 < sj.w ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
+        const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
+        const T vdote = vr * inv_r;
+        const T mu = vdote < (T)0 ? vdote : (T)0;
+        const T vs = ci + vj.w - a.beta * mu;
+        const T rsum = rhoi + rhoj;
+        T nu = 0;
+        if (visc) {
+            const T aij = (T)0.25 * (swi.x + wj.x) * (swi.y + wj.y);
+            nu = -aij * mu * vs / rsum;
+        }
+        const T mfg = cj.x * fi * gi + cj.z * gj;
+        const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
+        const T sr = sa * inv_r;
+        ax -= sr * dx;
+        ay -= sr * dy;
+        az -= sr * dz;
+        du += vdote * (cj.x * Ai * gi + (T)0.25 * nu * mfg);
+        // artificial conduction
+        const T Pj = ej.y;
+        const T psum = Pi + Pj;
+        const T acij = psum > (T)0 ? (Pi * swi.z + Pj * wj.z) / psum : (T)0;
+        const T vc = fabs(vdote) + sqrt((T)2 * fabs(Pi - Pj) / rsum);
+        du += acij * vc * (ui - ej.z) * mfg / rsum;
+    };
+    auto sweep = [&](int ns) {
+        pair_loop(m, ns, js, S, test, body);
+        tested += (unsigned long long)ns;
+    };
+    int flushes = 0;
+    const int ns = stage_tile<L_FSW, T, CAP>(m, a, t, bi, g, R * R, flushes, sweep);
+    sweep(ns);
+    ax = stream_sum(ax, q);
+    ay = stream_sum(ay, q);
+    az = stream_sum(az, q);
+    du = stream_sum(du, q);
+    const int nint = stream_sum(hits, q) - 1;
+    if (lead) {
+        a.out[0 * a.n + i] = ax;
+        a.out[1 * a.n + i] = ay;
+        a.out[2 * a.n + i] = az;
+        a.out[3 * a.n + i] = du;
+        a.iout[i] = nint;
+    }
+    ws.inside += (unsigned long long)wave_sum(lead ? nint : 0);
+    ws.tested += tested * (unsigned long long)tl.count;
+}
+
 // ----------------------------------------------------------------- drivers
 
 template <int LK, typename T, int CAP>
 __device__ __forceinline__ void run_tile(char* wm, const KArgs<T>& a, int t, WaveStats& ws) {
     if (LK == L_DENS) density_tile<T, CAP>(*(WaveMem<T, CAP, 1>*)wm, a, t, ws);
+    else if (LK == L_GSW) grad_sw_tile<T, CAP>(*(WaveMem<T, CAP, 3>*)wm, a, t, ws);
+    else if (LK == L_FSW) force_sw_tile<T, CAP>(*(WaveMem<T, CAP, 5>*)wm, a, t, ws);
     else force_tile<T, CAP>(*(WaveMem<T, CAP, 4>*)wm, a, t, ws);
 }
 
 // Register budgets matching what LDS allows (FP32): three wavefronts per
 // SIMD for the density kernel (its Newton accumulators would otherwise take
-// it just past the 168-register step), four for the gradient/force kernel.
+// it just past the 168-register step), four for the gradient/force kernel,
+// three for the two loops with switches.
+template <int LK>
+constexpr int loop_stats_index() {
+    return LK == L_DENS ? LOOP_DENSITY : (LK == L_GSW ? LOOP_GRADIENT : LOOP_FORCE);
+}
 template <int LK, typename T, int CAP>
 __global__ void __launch_bounds__(WPB * WAVE)
-SWSPH_WAVES_PER_EU(sizeof(T) != 4 ? 1 : (LK == L_DENS ? 3 : (LK == L_FORCE ? 4 : 1)))
+SWSPH_WAVES_PER_EU(sizeof(T) != 4 ? 1 : (LK == L_FORCE ? 4 : 3))
 k_loop(KArgs<T> a, int mode) {
     SWSPH_DYN_SHARED char smem[];
     constexpr size_t WMS = sizeof(WaveMem<T, CAP, LoopNV<LK>::NV>);
@@ -552,7 +748,7 @@ k_loop(KArgs<T> a, int mode) {
     char* wm = smem + wave * WMS;
     WaveStats ws;
     for_each_task(a, mode, [&](int t) { run_tile<LK, T, CAP>(wm, a, t, ws); });
-    ws.flush(a.cnt, LK);
+    ws.flush(a.cnt, loop_stats_index<LK>(), LK == L_FORCE);
 }
 
 int device_cu_count() {
@@ -671,6 +867,129 @@ template void launch_gf_tasks<float>(const BinPtrs&, const Scheme&, hipStream_t)
 template void launch_gf_tasks<double>(const BinPtrs&, const Scheme&, hipStream_t);
 template int launch_force<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_force<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+
+// ------------------------------------------------ time-dependent switches
+
+// Viscosity switch after the density loop (Sec. 2.1.3, Eq. 12-16), per
+// binned particle s (p = perm[s] its caller index): S = H^2 max(0, -(div v -
+// div v_prev) / dt), alpha_loc = alpha_max S / (v_sig_prev^2 + S); alpha_V
+// jumps up to alpha_loc or relaxes towards it as exp(-l c dt / H), floored
+// at alpha_min; B = |div v| / (|div v| + |curl v| + bal_eps c / H).
+// aux4[s] = (alpha_V(t + dt), B, 0, 0).
+template <typename T>
+__global__ void k_switch_visc(int64_t n, const int32_t* __restrict__ perm,
+                              const T* __restrict__ div_v, const T* __restrict__ div_prev,
+                              const T* __restrict__ cx, const T* __restrict__ cy,
+                              const T* __restrict__ cz, const T* __restrict__ vsig_prev,
+                              const T* __restrict__ av_in, const T* __restrict__ hs,
+                              const V4<T>* __restrict__ vel4, SwitchConsts sw, T eps, T gamma,
+                              V4<T>* __restrict__ aux4) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t p = perm[s];
+    const T H = eps * hs[s];
+    const T c = sqrt(gamma * (gamma - (T)1) * vel4[s].w);
+    const T dt = (T)sw.dt;
+    const T ddiv = (div_v[p] - div_prev[p]) / dt;
+    const T S = H * H * (ddiv < (T)0 ? -ddiv : (T)0);
+    const T vs = vsig_prev[p];
+    const T aloc = S > (T)0 ? (T)sw.av_max * S / (vs * vs + S) : (T)0;
+    T al = av_in[p];
+    al = aloc >= al ? aloc : aloc + (al - aloc) * exp(-(T)sw.ell * c * dt / H);
+    if (al < (T)sw.av_min) al = (T)sw.av_min;
+    const T dd = fabs(div_v[p]);
+    const T w = sqrt(cx[p] * cx[p] + cy[p] * cy[p] + cz[p] * cz[p]);
+    const T den = dd + w + (T)sw.bal_eps * c / H;
+    aux4[s] = V4<T>{al, den > (T)0 ? dd / den : (T)0, (T)0, (T)0};
+}
+
+// Conduction switch after the gradient loop (Sec. 2.1.4, Eq. 21, 23-24):
+// one explicit step d alpha_c/dt = beta_c H lap u / sqrt(u) - (alpha_c -
+// alpha_c,min) v_sig / H, then clamped to [alpha_c,min, alpha_c,max (1 -
+// alpha_V,ngb / alpha_V,max)].  gsw: the gradient outputs (v_sig, lap u,
+// alpha_V,ngb), binned.  Writes aux4[s].z.
+template <typename T>
+__global__ void k_switch_cond(int64_t n, const int32_t* __restrict__ perm,
+                              const T* __restrict__ ac_in, const T* __restrict__ hs,
+                              const V4<T>* __restrict__ vel4, const T* __restrict__ gsw,
+                              SwitchConsts sw, T eps, V4<T>* __restrict__ aux4) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t p = perm[s];
+    const T H = eps * hs[s];
+    const T u = vel4[s].w;
+    const T vs = gsw[s], lap = gsw[n + s], avn = gsw[2 * n + s];
+    const T a0 = ac_in[p];
+    const T src = u > (T)0 ? (T)sw.beta_c * H * lap / sqrt(u) : (T)0;
+    const T rate = src - (a0 - (T)sw.ac_min) * vs / H;
+    T a = a0 + (T)sw.dt * rate;
+    const T amax = (T)sw.ac_max * ((T)1 - avn / (T)sw.av_max);
+    if (a > amax) a = amax;
+    if (a < (T)sw.ac_min) a = (T)sw.ac_min;
+    aux4[s].z = a;
+}
+
+// The switch values back to the caller's order (p: caller index, rank[p]
+// its binned position); balsara and av_ngb may be null.
+template <typename T>
+__global__ void k_switch_out(int64_t n, const int32_t* __restrict__ rank,
+                             const V4<T>* __restrict__ aux4, const T* __restrict__ gsw,
+                             T* __restrict__ av, T* __restrict__ ac, T* __restrict__ balsara,
+                             T* __restrict__ av_ngb) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t s = rank[p];
+    const V4<T> x = aux4[s];
+    av[p] = x.x;
+    ac[p] = x.z;
+    if (balsara) balsara[p] = x.y;
+    if (av_ngb) av_ngb[p] = gsw[2 * n + s];
+}
+
+// The gradient and force loops with switches over the force task lists
+// (built first by launch_gf_tasks): viscosity switch, gradient loop,
+// conduction switch, force loop.  aux4 (the adjoint scratch region, free
+// outside the backward pass) holds (alpha_V, B, alpha_c, 0) per particle;
+// g_out receives v_sig, lap u and alpha_V,ngb.
+template <typename T>
+int launch_switch_loops(const BinPtrs& b, const Scheme& sc, const SwitchConsts& sw,
+                        const swsph_density_out* d, const swsph_switch_state* st, int mode,
+                        int lds_cap, hipStream_t s) {
+    if (b.n <= 0) return 0;
+    const unsigned blocks = (unsigned)((b.n + 255) / 256);
+    V4<T>* aux4 = (V4<T>*)b.adj;
+    hipLaunchKernelGGL(k_switch_visc<T>, dim3(blocks), dim3(256), 0, s, b.n, b.perm,
+                       (const T*)d->div_v, (const T*)st->div_v_prev, (const T*)d->curl_x,
+                       (const T*)d->curl_y, (const T*)d->curl_z, (const T*)st->v_sig_prev,
+                       (const T*)st->alpha_v, (const T*)b.hs, (const V4<T>*)b.vel4, sw,
+                       (T)sc.eps, (T)sc.gamma, aux4);
+    KArgs<T> a = make_args<T>(b, sc);
+    a.aux4 = aux4;
+    a.gout = (T*)b.g_out;
+    timer_begin(sc.timer, 1, s);
+    int r = launch_loop<L_GSW, T>(a, mode, lds_cap, 1, s);
+    timer_end(sc.timer, 1, s);
+    if (r) return r;
+    hipLaunchKernelGGL(k_switch_cond<T>, dim3(blocks), dim3(256), 0, s, b.n, b.perm,
+                       (const T*)st->alpha_c, (const T*)b.hs, (const V4<T>*)b.vel4,
+                       (const T*)b.g_out, sw, (T)sc.eps, aux4);
+    a.out = (T*)b.f_out;
+    a.iout = b.f_int;
+    timer_begin(sc.timer, 2, s);
+    r = launch_loop<L_FSW, T>(a, mode, lds_cap, 2, s);
+    timer_end(sc.timer, 2, s);
+    if (r) return r;
+    hipLaunchKernelGGL(k_switch_out<T>, dim3(blocks), dim3(256), 0, s, b.n, b.rank,
+                       (const V4<T>*)aux4, (const T*)b.g_out, (T*)st->alpha_v, (T*)st->alpha_c,
+                       (T*)st->balsara, (T*)st->alpha_v_ngb);
+    return 0;
+}
+template int launch_switch_loops<float>(const BinPtrs&, const Scheme&, const SwitchConsts&,
+                                        const swsph_density_out*, const swsph_switch_state*, int,
+                                        int, hipStream_t);
+template int launch_switch_loops<double>(const BinPtrs&, const Scheme&, const SwitchConsts&,
+                                         const swsph_density_out*, const swsph_switch_state*,
+                                         int, int, hipStream_t);
 
 // ------------------------------------------------- per-particle preparation
 

@@ -237,9 +237,10 @@ __device__ __forceinline__ GroupMap group_map(int c) {
     return q;
 }
 
-// loop kinds: forward loops and the three pair passes of the adjoint
-// (1 is unused: the gradient loop runs inside the force loop kernel)
-enum { L_DENS = 0, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5 };
+// loop kinds: forward loops, the three pair passes of the adjoint, and the
+// gradient and force loops with time-dependent switches (1 is unused: the
+// gradient loop of the plain scheme runs inside the force loop kernel)
+enum { L_DENS = 0, L_FORCE = 2, L_ADJA = 3, L_ADJC = 4, L_ADJD = 5, L_GSW = 6, L_FSW = 7 };
 
 template <int LK> struct LoopNV;
 template <> struct LoopNV<L_DENS> { static constexpr int NV = 1; };
@@ -247,9 +248,14 @@ template <> struct LoopNV<L_FORCE> { static constexpr int NV = 4; };
 template <> struct LoopNV<L_ADJA> { static constexpr int NV = 5; };
 template <> struct LoopNV<L_ADJC> { static constexpr int NV = 2; };
 template <> struct LoopNV<L_ADJD> { static constexpr int NV = 2; };
+template <> struct LoopNV<L_GSW> { static constexpr int NV = 3; };
+template <> struct LoopNV<L_FSW> { static constexpr int NV = 5; };
 
 // cull with the symmetric criterion r < max(H_i, H_j)?
-template <int LK> struct Symmetric { static constexpr bool value = LK >= L_FORCE; };
+template <int LK> struct Symmetric {
+    static constexpr bool value = LK == L_FORCE || LK == L_ADJA || LK == L_ADJC ||
+                                  LK == L_ADJD || LK == L_FSW;
+};
 
 template <typename T> __device__ __forceinline__ T int_as(int32_t v);
 template <> __device__ __forceinline__ float int_as<float>(int32_t v) { return __int_as_float(v); }
@@ -266,9 +272,11 @@ template <int LK, typename T> struct JData {
 template <int LK, typename T>
 __device__ __forceinline__ void gather_j(const KArgs<T>& a, int j, JData<LK, T>& r) {
     r.p = a.pos4[j];
-    if (LK == L_FORCE || LK == L_ADJA) r.v = a.vel4[j];
-    if (LK == L_FORCE || LK == L_ADJA) r.d = a.dens4[j];
-    if (LK >= L_ADJA) r.x = a.aux4[j];
+    constexpr bool VD = LK == L_FORCE || LK == L_ADJA || LK == L_GSW || LK == L_FSW;
+    constexpr bool X = LK == L_ADJA || LK == L_ADJC || LK == L_ADJD || LK == L_GSW || LK == L_FSW;
+    if (VD) r.v = a.vel4[j];
+    if (VD) r.d = a.dens4[j];
+    if (X) r.x = a.aux4[j];
     if (Symmetric<LK>::value) r.h = a.hs[j];
 }
 
@@ -339,6 +347,23 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int lt, const BoxInfo& bi, c
                 q1 = V4<T>{va.x, va.y, va.z, da.z};
                 q2 = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
                 q3 = V4<T>{da.x, int_as<T>(j), va.w, pa.w / da.x};
+            } else if (LK == L_GSW) {
+                // gradient loop with switches: (m_j / rho_j), c_j, u_j and
+                // alpha_V,j (aux4 = alpha_V, B, alpha_c, 0)
+                const V4<T> da = r.d;
+                q0 = V4<T>{xs, ys, zs, pa.w / da.x};
+                q1 = V4<T>{va.x, va.y, va.z, da.z};
+                q2 = V4<T>{va.w, r.x.x, (T)0, (T)0};
+            } else if (LK == L_FSW) {
+                // force loop with switches: the plain force record plus the
+                // pressure and the switch values of j
+                const V4<T> da = r.d;
+                const T Hj = mul_unfused(a.eps, r.h);
+                q0 = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
+                q1 = V4<T>{va.x, va.y, va.z, da.z};
+                q2 = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
+                q3 = V4<T>{da.x, (a.gamma - (T)1) * da.x * va.w, va.w, (T)0};
+                q4 = r.x;
             } else if (LK == L_ADJA) {
                 const V4<T> da = r.d;   // (rho, f, c, A)
                 const V4<T> wj = r.x;   // (dL/dax, dL/day, dL/daz, dL/ddu)
@@ -474,11 +499,13 @@ struct WaveStats {
     unsigned long long tested = 0, inside = 0, sweeps = 0, smax = 0, failed = 0, restages = 0;
     unsigned long long inside_g = 0;  // gradient pairs of the joint gradient/force loop
     unsigned long long listed = 0;    // density tiles swept over neighbour lists
-    __device__ void flush(Counters* c, int loop) const {
+    // loop: index of the statistics (LOOP_*); joint: the joint gradient/force
+    // kernel, whose tests serve both loops
+    __device__ void flush(Counters* c, int loop, bool joint) const {
         if (lane_id() != 0) return;
         if (tested) atomicAdd(&c->pairs_tested[loop], tested);
         if (inside) atomicAdd(&c->pairs_inside[loop], inside);
-        if (loop == L_FORCE) {
+        if (joint) {
             if (tested) atomicAdd(&c->pairs_tested[LOOP_GRADIENT], tested);
             if (inside_g) atomicAdd(&c->pairs_inside[LOOP_GRADIENT], inside_g);
         }

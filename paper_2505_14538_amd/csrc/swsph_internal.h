@@ -83,7 +83,7 @@ struct Layout {
     // sorted-order results
     uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
     uint64_t d_int;     // 2 arrays of int32: nngb iters
-    uint64_t g_out;     // 2 arrays of T
+    uint64_t g_out;     // 3 arrays of T (the third: alpha_V,ngb of the switch loops)
     uint64_t f_out;     // 4 arrays of T
     uint64_t f_int;     // 1 array of int32
     uint64_t adj;       // adjoint scratch: 16 arrays of T

@@ -86,6 +86,22 @@ class InputGrad(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("gx", "gy", "gz", "gvx", "gvy", "gvz", "gu", "gm")]
 
 
+class SwitchParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("dt", "av_max", "av_min", "ell", "beta_c", "ac_min", "ac_max", "bal_eps")]
+
+
+# switch constants: the decay length l = 0.05 is the paper's (Sec. 2.1.3);
+# the others are conventions the paper does not fix
+SWITCH_DEFAULTS = {"av_max": 2.0, "av_min": 0.0, "ell": 0.05, "beta_c": 1.0, "ac_min": 0.0,
+                   "ac_max": 1.0, "bal_eps": 1e-4}
+
+
+class SwitchState(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in
+                ("alpha_v", "alpha_c", "div_v_prev", "v_sig_prev", "balsara", "alpha_v_ngb")]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
                 ("pairs_tested", ctypes.c_uint64 * 4), ("pairs_inside", ctypes.c_uint64 * 4),
@@ -121,6 +137,9 @@ _lib.swsph_force_backward.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(Fo
                                       _P(InputGrad), _vp, _vp]
 _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut), _P(ForceOut),
                             _vp, _vp]
+_lib.swsph_gradient_force_sw.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(SwitchParams),
+                                         _P(SwitchState), _P(GradientOut), _P(ForceOut), _vp,
+                                         _vp]
 _lib.swsph_step_static.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut),
                                    _P(ForceOut), _vp]
 _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
@@ -132,7 +151,7 @@ _lib.swsph_reset_timers.argtypes = [_vp]
 EXPORTS = ["swsph_version", "swsph_last_error", "swsph_config_default", "swsph_plan_create",
            "swsph_plan_destroy", "swsph_workspace_bytes", "swsph_bin", "swsph_density",
            "swsph_gradient", "swsph_force", "swsph_force_backward", "swsph_step",
-           "swsph_step_static", "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
+           "swsph_step_static", "swsph_gradient_force_sw", "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
            "swsph_kernel_times", "swsph_reset_timers"]
 
 
@@ -323,6 +342,32 @@ class Plan:
         _check(_lib.swsph_force(self.h, ctypes.byref(pc), ctypes.byref(dc), ctypes.byref(fo),
                                 self._ws_ptr(), _stream()))
         return o
+
+    def gradient_force_sw(self, p: DeviceParticles, dens, dt: float, state, **params):
+        """Gradient and force loops with the time-dependent switches
+        (swsph_gradient_force_sw).  state: dict of device tensors alpha_v and
+        alpha_c (read at t, overwritten with t + dt), div_v_prev, v_sig_prev;
+        returns (gradient outputs incl. alpha_v_ngb, force outputs, balsara)."""
+        torch = _torch()
+        n = p.n
+        prm = dict(SWITCH_DEFAULTS)
+        prm.update(params)
+        sp = SwitchParams(dt=dt, **prm)
+        g = {"v_sig": self._alloc(n), "lap_u": self._alloc(n), "alpha_v_ngb": self._alloc(n)}
+        f = {k: self._alloc(n) for k in ("ax", "ay", "az", "dudt")}
+        f["nint"] = self._alloc(n, torch.int32)
+        bal = self._alloc(n)
+        st = SwitchState(_ptr(state["alpha_v"]), _ptr(state["alpha_c"]),
+                         _ptr(state["div_v_prev"]), _ptr(state["v_sig_prev"]), _ptr(bal),
+                         _ptr(g["alpha_v_ngb"]))
+        go = GradientOut(_ptr(g["v_sig"]), _ptr(g["lap_u"]))
+        fo = ForceOut(**{k: _ptr(v) for k, v in f.items()})
+        pc = p.c()
+        dc = self._dens_c(dens)
+        _check(_lib.swsph_gradient_force_sw(self.h, ctypes.byref(pc), ctypes.byref(dc),
+                                            ctypes.byref(sp), ctypes.byref(st), ctypes.byref(go),
+                                            ctypes.byref(fo), self._ws_ptr(), _stream()))
+        return g, f, bal
 
     def step(self, p: DeviceParticles, gradient: bool = True, force: bool = True, out=None):
         """bin + density + gradient + force in one call.  The library captures

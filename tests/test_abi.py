@@ -117,3 +117,35 @@ def test_static_step_rejects_oversized_set_on_host(S):
                                     None) == -1
     assert b"static scratch" in S._lib.swsph_last_error()
     assert S._lib.swsph_step_static(p.h, ctypes.byref(pc), None, None, None, None) == -1
+
+
+def test_switch_call_rejects_bad_arguments_on_host(S):
+    """swsph_gradient_force_sw checks its parameters and state on the host."""
+    p = S.Plan()
+    pc = S.ParticlesC()
+    pc.n = 100
+    pc.n_box = 1
+    bs = np.array([1.0])
+    pc.box_size = bs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    pc.x = pc.y = pc.z = pc.vx = pc.vy = pc.vz = pc.m = pc.u = 1024
+    d = S.DensityOut()
+    d.h = d.rho = d.f = 4096
+    sp = S.SwitchParams(dt=1e-3, **S.SWITCH_DEFAULTS)
+    st = S.SwitchState(1024, 1024, 1024, 1024, None, None)
+    go = S.GradientOut(1024, 1024)
+    fo = S.ForceOut(1024, 1024, 1024, 1024, None)
+    ws = ctypes.c_void_p(256)
+    call = lambda: S._lib.swsph_gradient_force_sw(p.h, ctypes.byref(pc), ctypes.byref(d),
+                                                  ctypes.byref(sp), ctypes.byref(st),
+                                                  ctypes.byref(go), ctypes.byref(fo), ws, None)
+    assert call() == -1                              # density lacks div v / curl v
+    d.div_v = d.curl_x = d.curl_y = d.curl_z = 4096
+    assert call() == -3                              # no bin on this plan
+    sp.dt = 0.0
+    assert call() == -1
+    sp.dt = 1e-3
+    sp.ac_max = -1.0
+    assert call() == -1
+    sp.ac_max = 1.0
+    st.alpha_c = None
+    assert call() == -1
