@@ -19,7 +19,8 @@ h as the guess), the autotuner's choice, the roofline entry of the dominant
 kernel (with FP32 VALU counter figures and HBM traffic from the committed
 rocprofv3 summaries while the kernel sources match them), the many-boxes set
 (256 boxes in one launch per loop), the differentiation set (forward and
-adjoint) and the FP64 oracle on the host cores.
+adjoint), the Gresho-Chan vortex integrated with the switch loops, and the
+FP64 oracle on the host cores.
 """
 import argparse
 import json
@@ -230,6 +231,38 @@ def diff_leg(S, W, args):
             "forward_ms": float(np.median(fwd)), "adjoint_ms": float(np.median(bwd))}
 
 
+def gresho_leg(args):
+    """The Gresho-Chan vortex (Sec. 3.1, Eq. 27-28) at the resolution of the
+    paper's Fig. 6, 128^3 particles, integrated to t = 0.1 with the switch
+    loops: time per leapfrog step and the error of the binned profiles."""
+    import torch
+    from paper_2505_14538_amd import gresho as G
+    from paper_2505_14538_amd import workloads as W
+    log("gresho 128^3 to t = 0.1")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    marks = {}
+
+    def on_step(k, t):
+        if k == 1:
+            ev[0].record()
+        marks["last"] = k
+
+    out = G.run(nside=128, t_end=0.1, on_step=on_step)
+    ev[1].record()
+    torch.cuda.synchronize()
+    steps = out["steps"]
+    ms = ev[0].elapsed_time(ev[1]) / max(1, steps - 1)
+    pr = G.profile(out["x"], out["y"], out["vx"], out["vy"], out["P"])
+    va, Pa = W.gresho_profiles(pr["r"])
+    inner = pr["r"] < 0.45
+    log("gresho: %d steps, %.3f ms per step" % (steps, ms))
+    return {"workload": "Gresho-Chan vortex, 128^3 lattice, switches on, leapfrog to t = 0.1",
+            "n": out["n"], "steps": steps, "dt": out["dt"], "ms_per_step": ms,
+            "v_phi_mean_abs_err": float(np.mean(np.abs(pr["v"] - va)[inner])),
+            "pressure_mean_abs_err": float(np.mean(np.abs(pr["P"] - Pa)[inner])),
+            "energy_drift": (out["energy"] - out["energy0"]) / out["energy0"]}
+
+
 def run(args):
     import torch
     from paper_2505_14538_amd import swsph as S
@@ -379,6 +412,7 @@ def run(args):
     if legs and not args.no_extra:
         res["many_boxes"] = many_boxes_leg(S, W, args)
         res["differentiation"] = diff_leg(S, W, args)
+        res["gresho"] = gresho_leg(args)
     if legs and not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(parts)
@@ -392,7 +426,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the many-boxes and differentiation legs")
+                    help="skip the many-boxes, differentiation and Gresho legs")
     ap.add_argument("--only-step", action="store_true",
                     help="only the batched and the timed eager step (profiler runs)")
     ap.add_argument("--no-per-task", action="store_true",

@@ -296,6 +296,22 @@ int swsph_gradient_force_sw(swsph_plan* plan, const swsph_particles* p,
                             swsph_switch_state* st, swsph_gradient_out* go,
                             swsph_force_out* fo, void* ws, void* stream);
 
+/* Leapfrog time integration between force evaluations (kick-drift-kick;
+ * the paper's correctness test integrates the Gresho-Chan vortex in time
+ * with SWIFT, Sec. 3.1, Fig. 6): v += a dt_kick and u += du/dt dt_kick
+ * (skipped when dt_kick == 0; then a and dudt may be NULL), then
+ * x += v dt_drift with the kicked v, wrapped into [0, box_size[b]) of the
+ * particle's box b (skipped when dt_drift == 0).  All arrays are device
+ * arrays of n elements of the plan's dtype in the caller's order, updated
+ * in place; box_id (device, nullable when n_box == 1) and box_size (host,
+ * n_box <= 64 entries) as in swsph_particles.  No binning needed; the next
+ * swsph_bin takes the moved particles.  Argument errors: SWSPH_E_ARG. */
+int swsph_kick_drift(const swsph_plan* plan, int64_t n, void* x, void* y, void* z, void* vx,
+                     void* vy, void* vz, void* u, const void* ax, const void* ay,
+                     const void* az, const void* dudt, double dt_kick, double dt_drift,
+                     const int32_t* box_id, int32_t n_box, const double* box_size,
+                     void* stream);
+
 /* One whole step: bin, density, gradient and force (go / fo may be NULL to
  * skip that loop).  The step is captured once into a HIP graph (on a
  * stream the plan creates) and replayed on `stream` while the particle,

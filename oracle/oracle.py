@@ -427,3 +427,39 @@ def force_sw(p, dens, av, B, ac, params: Params = Params(), idx=None):
             res[k][ib] = loc[k]
         res["nint"][ib] = ni
     return res
+
+
+def kdk_step(p, f0, dt, state, sw: SwitchParams, params: Params = Params()):
+    """One leapfrog (kick-drift-kick) step of the particles p (float64 arrays,
+    one periodic box) with the switch loops: v and u kicked by the forces f0
+    over dt/2, positions drifted by dt with the kicked v (wrapped into the
+    box), density, gradient loop, switch updates and force loop at the new
+    state, then the second half kick.  state: dict alpha_v, alpha_c,
+    div_v_prev, v_sig_prev (time t).  Returns (particles, density, gradient,
+    force, new state)."""
+    L = float(p.box_size[0])
+    q = p.subset(np.arange(p.n))
+    h2 = 0.5 * dt
+    vx = q.vx + f0["ax"] * h2
+    vy = q.vy + f0["ay"] * h2
+    vz = q.vz + f0["az"] * h2
+    u = q.u + f0["dudt"] * h2
+    q.x = np.mod(q.x + vx * dt, L)
+    q.y = np.mod(q.y + vy * dt, L)
+    q.z = np.mod(q.z + vz * dt, L)
+    q.vx, q.vy, q.vz, q.u = vx, vy, vz, u
+    sw = SwitchParams(**{**sw.__dict__, "dt": dt})
+    dens = density(q, params)
+    grad = gradient(q, dens, params)
+    sv = switch_visc(q, dens, sw, state["div_v_prev"], state["v_sig_prev"], state["alpha_v"],
+                     params)
+    ngb = alpha_ngb(q, dens, sv["alpha_v"], params)
+    ac = switch_cond(q, dens, grad, sw, ngb, state["alpha_c"], params)
+    f1 = force_sw(q, dens, sv["alpha_v"], sv["balsara"], ac, params)
+    q.vx = q.vx + f1["ax"] * h2
+    q.vy = q.vy + f1["ay"] * h2
+    q.vz = q.vz + f1["az"] * h2
+    q.u = q.u + f1["dudt"] * h2
+    new_state = {"alpha_v": sv["alpha_v"], "alpha_c": ac, "div_v_prev": dens["div_v"],
+                 "v_sig_prev": grad["v_sig"], "balsara": sv["balsara"], "alpha_v_ngb": ngb}
+    return q, dens, grad, f1, new_state

@@ -664,6 +664,41 @@ int swsph_gradient_force_sw(swsph_plan* pl, const swsph_particles* p, const swsp
     return hip_check(hipGetLastError(), "gradient+force with switches");
 }
 
+int swsph_kick_drift(const swsph_plan* pl, int64_t n, void* x, void* y, void* z, void* vx,
+                     void* vy, void* vz, void* u, const void* ax, const void* ay,
+                     const void* az, const void* dudt, double dt_kick, double dt_drift,
+                     const int32_t* box_id, int32_t n_box, const double* box_size,
+                     void* stream) {
+    if (!pl) return fail(SWSPH_E_ARG, "plan is NULL");
+    if (n < 0) return fail(SWSPH_E_ARG, "n < 0");
+    if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+        return fail(SWSPH_E_ARG, "time steps must be finite");
+    if (n_box < 1 || n_box > DRIFT_MAX_BOXES)
+        return fail(SWSPH_E_ARG, "n_box must be in [1, %d]", DRIFT_MAX_BOXES);
+    if (n_box > 1 && !box_id) return fail(SWSPH_E_ARG, "box_id is required when n_box > 1");
+    if (!box_size) return fail(SWSPH_E_ARG, "box_size is NULL");
+    DriftBoxes boxes{};
+    for (int b = 0; b < n_box; ++b) {
+        if (!(box_size[b] > 0) || !std::isfinite(box_size[b]))
+            return fail(SWSPH_E_ARG, "box_size[%d] must be > 0", b);
+        boxes.L[b] = box_size[b];
+    }
+    if (n > 0) {
+        if (!vx || !vy || !vz) return fail(SWSPH_E_ARG, "velocities are NULL");
+        if (dt_kick != 0.0 && (!u || !ax || !ay || !az || !dudt))
+            return fail(SWSPH_E_ARG, "a kick needs u, a and du/dt");
+        if (dt_drift != 0.0 && (!x || !y || !z)) return fail(SWSPH_E_ARG, "positions are NULL");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (pl->cfg.dtype == SWSPH_F64)
+        launch_kick_drift<double>(n, x, y, z, vx, vy, vz, u, ax, ay, az, dudt, dt_kick, dt_drift,
+                                  box_id, n_box, boxes, s);
+    else
+        launch_kick_drift<float>(n, x, y, z, vx, vy, vz, u, ax, ay, az, dudt, dt_kick, dt_drift,
+                                 box_id, n_box, boxes, s);
+    return hip_check(hipGetLastError(), "kick/drift");
+}
+
 int swsph_kernel_times(swsph_plan* pl, double ms[4], uint64_t launches[4], void* stream) {
     if (!pl || !ms || !launches) return fail(SWSPH_E_ARG, "plan, ms and launches are required");
     for (int k = 0; k < 4; ++k) { ms[k] = 0.0; launches[k] = 0; }

@@ -134,4 +134,16 @@ int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* 
                     const swsph_density_out* d, int lds_cap, hipStream_t s);
 int device_cu_count();
 
+// integrate.hip: the leapfrog kick (v += a dt_kick, u += du/dt dt_kick) and
+// drift (x += v dt_drift, wrapped into the particle's box)
+constexpr int DRIFT_MAX_BOXES = 64;
+struct DriftBoxes {
+    double L[DRIFT_MAX_BOXES];
+};
+template <typename T>
+void launch_kick_drift(int64_t n, void* x, void* y, void* z, void* vx, void* vy, void* vz, void* u,
+                       const void* ax, const void* ay, const void* az, const void* dudt,
+                       double dt_kick, double dt_drift, const int32_t* box_id, int32_t n_box,
+                       const DriftBoxes& boxes, hipStream_t s);
+
 }  // namespace swsph

@@ -140,6 +140,8 @@ _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut)
 _lib.swsph_gradient_force_sw.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(SwitchParams),
                                          _P(SwitchState), _P(GradientOut), _P(ForceOut), _vp,
                                          _vp]
+_lib.swsph_kick_drift.argtypes = [_vp, ctypes.c_int64] + [_vp] * 11 + \
+    [ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int32, _P(ctypes.c_double), _vp]
 _lib.swsph_step_static.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut),
                                    _P(ForceOut), _vp]
 _lib.swsph_read_stats.argtypes = [_vp, _vp, _P(Stats), _vp]
@@ -151,7 +153,8 @@ _lib.swsph_reset_timers.argtypes = [_vp]
 EXPORTS = ["swsph_version", "swsph_last_error", "swsph_config_default", "swsph_plan_create",
            "swsph_plan_destroy", "swsph_workspace_bytes", "swsph_bin", "swsph_density",
            "swsph_gradient", "swsph_force", "swsph_force_backward", "swsph_step",
-           "swsph_step_static", "swsph_gradient_force_sw", "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
+           "swsph_step_static", "swsph_gradient_force_sw", "swsph_kick_drift",
+           "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
            "swsph_kernel_times", "swsph_reset_timers"]
 
 
@@ -368,6 +371,18 @@ class Plan:
                                             ctypes.byref(sp), ctypes.byref(st), ctypes.byref(go),
                                             ctypes.byref(fo), self._ws_ptr(), _stream()))
         return g, f, bal
+
+    def kick_drift(self, p: DeviceParticles, f, dt_kick: float, dt_drift: float):
+        """Leapfrog update of p in place (swsph_kick_drift): v += a dt_kick,
+        u += du/dt dt_kick with the force outputs f (dict; may be None when
+        dt_kick == 0), then x += v dt_drift wrapped into the box."""
+        pc = p.c()
+        a = (None, None, None, None) if f is None else \
+            (_ptr(f["ax"]), _ptr(f["ay"]), _ptr(f["az"]), _ptr(f["dudt"]))
+        _check(_lib.swsph_kick_drift(self.h, p.n, _ptr(p.x), _ptr(p.y), _ptr(p.z), _ptr(p.vx),
+                                     _ptr(p.vy), _ptr(p.vz), _ptr(p.u), *a, float(dt_kick),
+                                     float(dt_drift), _ptr(p.box_id), pc.n_box, pc.box_size,
+                                     _stream()))
 
     def step(self, p: DeviceParticles, gradient: bool = True, force: bool = True, out=None):
         """bin + density + gradient + force in one call.  The library captures

@@ -237,6 +237,35 @@ def diff(nside: int = 64, seed: Optional[int] = None):
     return p, w, c
 
 
+def gresho_profiles(r):
+    """Azimuthal velocity and pressure of the Gresho-Chan vortex (Sec. 3.1,
+    Eq. 27-28) at cylindrical radius r (rho = 1): v = 5r, 2 - 5r, 0 and
+    P = 5 + 12.5 r^2, 9 - 4 ln 0.2 + 12.5 r^2 - 20 r + 4 ln r, 3 + 4 ln 2 on
+    [0, 0.2), [0.2, 0.4), [0.4, inf)."""
+    r = np.asarray(r, dtype=np.float64)
+    v = np.where(r < 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))
+    rr = np.maximum(r, 1e-300)
+    P = np.where(r < 0.2, 5.0 + 12.5 * r * r,
+                 np.where(r < 0.4,
+                          9.0 - 4.0 * np.log(0.2) + 12.5 * r * r - 20.0 * r + 4.0 * np.log(rr),
+                          3.0 + 4.0 * np.log(2.0)))
+    return v, P
+
+
+def gresho(nside: int = 64, gamma: float = 5.0 / 3.0) -> Particles:
+    """Gresho-Chan vortex initial conditions (Sec. 3.1): nside^3 particles on
+    a cubic lattice in the periodic unit box, density 1 (m = 1/N), the
+    vortex axis parallel to z through (1/2, 1/2), azimuthal velocity and
+    pressure of Eq. 27-28, u = P / ((gamma - 1) rho)."""
+    pos = lattice(nside)
+    n = pos.shape[0]
+    dx, dy = pos[:, 0] - 0.5, pos[:, 1] - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    v, P = gresho_profiles(r)
+    vel = np.stack([-v * dy / r, v * dx / r, np.zeros(n)], axis=1)
+    return _pack(pos, vel, P / (gamma - 1.0), np.full(n, 1.0 / n), 1.0, "gresho", 0)
+
+
 def shuffled(p: Particles, seed: int = 7) -> Particles:
     """Same particles in a random order (tests that results do not depend on
     input order)."""

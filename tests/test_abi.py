@@ -149,3 +149,19 @@ def test_switch_call_rejects_bad_arguments_on_host(S):
     sp.ac_max = 1.0
     st.alpha_c = None
     assert call() == -1
+
+
+def test_kick_drift_rejects_bad_arguments_on_host(S):
+    p = S.Plan()
+    bs = np.array([1.0])
+    bsp = bs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    a = [1024] * 11
+    kd = S._lib.swsph_kick_drift
+    assert kd(p.h, 10, *a, 0.1, 0.1, None, 2, bsp, None) == -1        # box ids missing
+    assert kd(p.h, 10, *a, 0.1, 0.1, None, 65, bsp, None) == -1       # too many boxes
+    assert kd(p.h, 10, *a, float("nan"), 0.1, None, 1, bsp, None) == -1
+    b = list(a)
+    b[7] = None                                                        # ax missing
+    assert kd(p.h, 10, *b, 0.1, 0.0, None, 1, bsp, None) == -1
+    bs[0] = -1.0
+    assert kd(p.h, 10, *a, 0.1, 0.1, None, 1, bsp, None) == -1
