@@ -113,7 +113,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
     T S0 = 0, S1 = 0, S2 = 0, Sr = 0, Sdr = 0, Dv = 0, Cx = 0, Cy = 0, Cz = 0;
     int cnt = 0;
     unsigned long long tested = 0;      // per i-particle
-    unsigned long long tested_all = 0;  // over the tile
+    unsigned long long tested_lane = 0;  // list evaluations of this lane's slot (lead lanes)
     T H = eps * h;
     T H2 = act ? mul_unfused(H, H) : (T)-1;
     T invH = (T)1 / H;
@@ -311,7 +311,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
             }
             evals += nl;
             // tests: the list pass plus every list evaluation
-            tested_all += (unsigned long long)wave_sum(lead ? evals : 0);
+            tested_lane += lead ? (unsigned long long)evals : 0ull;
         } else {
             vi = a.vel4[i];
             sweep(ns);
@@ -364,32 +364,35 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
         if (!conv && !pend && act) failed = true;
         // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
         if (lead) {
-            const T Hh = eps * h;
-            const T iH = (T)1 / Hh;
+            // reciprocals (the hardware's in FP32, within an ulp) instead of
+            // divisions
+            const T ih = step_rcp(h);
+            const T iH = ih / eps;
             const T k3 = cnorm * iH * iH * iH;
             const T k5 = k3 * iH * iH;
             const T rho = k3 * Sr;
-            const T drho = -k3 * Sdr / h;
+            const T irho = step_rcp(rho);
+            const T drho = -k3 * Sdr * ih;
             const int64_t n = a.n;
             T* o = a.out;
             o[0 * n + i] = h;
             o[1 * n + i] = rho;
             o[2 * n + i] = drho;
             o[3 * n + i] = k3 * S0;
-            o[4 * n + i] = -k3 * S1 / h;
-            o[5 * n + i] = -k5 * Dv / rho;
-            o[6 * n + i] = k5 * Cx / rho;
-            o[7 * n + i] = k5 * Cy / rho;
-            o[8 * n + i] = k5 * Cz / rho;
-            o[9 * n + i] = (T)1 / ((T)1 + h * drho / ((T)3 * rho));
+            o[4 * n + i] = -k3 * S1 * ih;
+            o[5 * n + i] = -k5 * Dv * irho;
+            o[6 * n + i] = k5 * Cx * irho;
+            o[7 * n + i] = k5 * Cy * irho;
+            o[8 * n + i] = k5 * Cz * irho;
+            o[9 * n + i] = step_rcp((T)1 + h * drho * irho * ((T)1 / (T)3));
             a.iout[0 * n + i] = cnt - 1;
             a.iout[1 * n + i] = failed ? -iters : iters;
             a.hs[i] = pend ? want : h;
         }
         const unsigned long long pmask = ballot(pend);
         const unsigned long long fmask = ballot(failed && js == 0);
-        const T wmax = wave_max(pend ? want : (T)0);
-        const unsigned long long ins = (unsigned long long)wave_sum(lead ? cnt : 0);
+        T wmax = 0;
+        if (pmask) wmax = wave_max(pend ? want : (T)0);
         if (lane == 0) {
             if (pmask) {
                 T Rn = eps * wmax * (T)1.0625;
@@ -402,10 +405,12 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
             if (fmask) latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
         }
         ws.restages += pmask ? 1ull : 0ull;
-        ws.tested += tested * (unsigned long long)tl.count + tested_all;
-        ws.inside += ins;
+        ws.tested += tested * (unsigned long long)tl.count;
+        // per-lane statistics, reduced over the wavefront once per launch
+        ws.lane_tested += tested_lane;
+        ws.lane_inside += lead ? (unsigned long long)cnt : 0ull;
+        ws.lane_smax = max(ws.lane_smax, iters);
         ws.sweeps += (unsigned long long)(iters - iters0);
-        ws.smax = max(ws.smax, (unsigned long long)wave_max(iters));
         ws.failed += (unsigned long long)__popcll(fmask);
     };
     density_sweeps();

@@ -499,18 +499,24 @@ struct WaveStats {
     unsigned long long tested = 0, inside = 0, sweeps = 0, smax = 0, failed = 0, restages = 0;
     unsigned long long inside_g = 0;  // gradient pairs of the joint gradient/force loop
     unsigned long long listed = 0;    // density tiles swept over neighbour lists
+    // per-lane parts (density loop), reduced over the wavefront at the flush
+    unsigned long long lane_tested = 0, lane_inside = 0;
+    int lane_smax = 0;
     // loop: index of the statistics (LOOP_*); joint: the joint gradient/force
     // kernel, whose tests serve both loops
     __device__ void flush(Counters* c, int loop, bool joint) const {
+        // every lane: the wavefront reductions of the per-lane parts
+        const unsigned long long lt = wave_sum(lane_tested), li = wave_sum(lane_inside);
+        const unsigned long long sm = (unsigned long long)max(smax, (unsigned long long)wave_max(lane_smax));
         if (lane_id() != 0) return;
-        if (tested) atomicAdd(&c->pairs_tested[loop], tested);
-        if (inside) atomicAdd(&c->pairs_inside[loop], inside);
+        if (tested + lt) atomicAdd(&c->pairs_tested[loop], tested + lt);
+        if (inside + li) atomicAdd(&c->pairs_inside[loop], inside + li);
         if (joint) {
             if (tested) atomicAdd(&c->pairs_tested[LOOP_GRADIENT], tested);
             if (inside_g) atomicAdd(&c->pairs_inside[LOOP_GRADIENT], inside_g);
         }
         if (sweeps) atomicAdd(&c->newton_sweeps, sweeps);
-        if (smax) atomicMax(&c->newton_max, smax);
+        if (sm) atomicMax(&c->newton_max, sm);
         if (failed) atomicAdd(&c->newton_failed, failed);
         if (restages) atomicAdd(&c->restages, restages);
         if (listed) atomicAdd(&c->dens_listed, listed);

@@ -189,6 +189,9 @@ template <typename T> __device__ __forceinline__ T wave_min(T v) {
     for (int m = 32; m >= 1; m >>= 1) { T o = shfl_xor(v, m); v = o < v ? o : v; }
     return v;
 }
+__device__ __forceinline__ unsigned long long shfl_xor(unsigned long long v, int m) {
+    return __shfl_xor(v, m, WAVE);
+}
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
