@@ -117,6 +117,12 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
     T H = eps * h;
     T H2 = act ? mul_unfused(H, H) : (T)-1;
     T invH = (T)1 / H;
+    // Halley steps below ds_pred (in log h) are taken without a confirming
+    // sweep when allowed: their error, about the step's cube, stays well
+    // inside h_tol, and the full sweep at the new h checks the stop
+    // criterion anyway (a particle that fails it iterates on)
+    bool pred = false, allow_pred = false;
+    const T ds_pred = cbrt((T)2 * a.h_tol);
     // a pair inside the support: sj the staged image position, pj and vj the
     // partner's pos4 (mass in w) and vel4; vi the particle's own velocity
     V4<T> vi{};
@@ -161,6 +167,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
     // One Halley update per lane from the sums of the sweep at h (over the
     // streams of its i-particle).
     auto newton = [&](T S0r, T S1r, T S2r) {
+        pred = false;
         if (conv || pend) return;
         const T G = S0r;
         if (fabs(G - Tt) <= a.h_tol * Tt) {
@@ -201,6 +208,9 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
         } else if (fabs(hn - h) <= tiny * h) {
             conv = true;
         } else {
+            // a small accepted step leaves an error of order its cube
+            // (Halley): the next sweep would only confirm it
+            pred = allow_pred && ok && fabs(ds) <= ds_pred;
             h = hn;
         }
     };
@@ -251,65 +261,91 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
             const int nmax = uniform(wave_max(nl));
             const uint16_t* el = &m.ent[q.li * capl];
             int evals = 0;
-            for (int sweeps = 1; sweeps <= a.h_max_iter; ++sweeps) {
-                ++iters;
-                // sweep at h: n and its first two log-h derivatives only
-                T s0 = 0, s1 = 0, s2 = 0;
-                for (int t0 = 0; t0 < nmax; t0 += U * S) {
-                    V4<T> sj[U];
-                    bool ok[U];
+            int sweeps = 0;
+            allow_pred = true;
+            for (int round = 0; round < 2; ++round) {
+                // light sweeps until every particle has converged, needs a
+                // wider staged set, or took a small step
+                for (;;) {
+                    ++sweeps;
+                    ++iters;
+                    // sweep at h: n and its first two log-h derivatives only
+                    T s0 = 0, s1 = 0, s2 = 0;
+                    for (int t0 = 0; t0 < nmax; t0 += U * S) {
+                        V4<T> sj[U];
+                        bool ok[U];
     #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int e = t0 + u * S + js;
-                        ok[u] = e < nl;
-                        sj[u] = m.s[0][ok[u] ? el[e] : 0];
-                    }
+                        for (int u = 0; u < U; ++u) {
+                            const int e = t0 + u * S + js;
+                            ok[u] = e < nl;
+                            sj[u] = m.s[0][ok[u] ? el[e] : 0];
+                        }
     #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const T r2 = dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y, pi.z - sj[u].z);
-                        if (ok[u] && r2 < H2) {
-                            const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
-                            const T qq = r2 * inv_r * invH;
-                            T w, s1v, gq;
-                            m4_terms(qq, H * inv_r, w, s1v, gq);
-                            s0 += w;
-                            s1 += s1v;
-                            s2 += m4_q2w2(qq);
+                        for (int u = 0; u < U; ++u) {
+                            const T r2 =
+                                dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y, pi.z - sj[u].z);
+                            if (ok[u] && r2 < H2) {
+                                const T inv_r = r2 > (T)0 ? fast_rsqrt(r2) : (T)0;
+                                const T qq = r2 * inv_r * invH;
+                                T w, s1v, gq;
+                                m4_terms(qq, H * inv_r, w, s1v, gq);
+                                s0 += w;
+                                s1 += s1v;
+                                s2 += m4_q2w2(qq);
+                            }
                         }
                     }
+                    evals += nl;
+                    newton(group_sum(s0, S), group_sum(s1, S), group_sum(s2, S));
+                    if (ballot(!conv && !pend && !pred) == 0ull) break;
+                    if (sweeps >= a.h_max_iter) break;
+                    next_h();
+                }
+                next_h();  // a small step moved h (the others keep theirs)
+                vi = a.vel4[i];
+                // the full sums at the final h (partner data from global
+                // memory, the loads of UF entries issued together)
+                zero();
+                for (int t0 = 0; t0 < nmax; t0 += UF * S) {
+                    V4<T> sj[UF], pj[UF], vj[UF];
+                    bool in[UF];
+    #pragma unroll
+                    for (int u = 0; u < UF; ++u) {
+                        const int e = t0 + u * S + js;
+                        const bool ok = e < nl;
+                        sj[u] = m.s[0][ok ? el[e] : 0];
+                        in[u] = ok && dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y,
+                                                    pi.z - sj[u].z) < H2;
+                    }
+    #pragma unroll
+                    for (int u = 0; u < UF; ++u) {
+                        int j = in[u] ? as_int<T>(sj[u].w) : 0;
+                        if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid list
+                        pj[u] = a.pos4[j];
+                        vj[u] = a.vel4[j];
+                    }
+    #pragma unroll
+                    for (int u = 0; u < UF; ++u)
+                        if (in[u]) body(sj[u], pj[u], vj[u]);
                 }
                 evals += nl;
-                newton(group_sum(s0, S), group_sum(s1, S), group_sum(s2, S));
-                if (ballot(!conv && !pend) == 0ull) break;
-                if (sweeps == a.h_max_iter) break;
+                if (round == 1) break;
+                // a particle whose last step was small checks the stop
+                // criterion on the full sums; one that fails it iterates on
+                // from them (no small-step exits then) and the full sweep is
+                // repeated (identical sums for the others)
+                const T G = group_sum(S0, S), G1 = group_sum(S1, S), G2 = group_sum(S2, S);
+                bool again = false;
+                if (pred) {
+                    pred = false;
+                    if (fabs(G - Tt) <= a.h_tol * Tt) conv = true;
+                    else again = true;
+                }
+                if (ballot(again) == 0ull || sweeps >= a.h_max_iter) break;
+                allow_pred = false;
+                if (again) newton(G, G1, G2);
                 next_h();
             }
-            vi = a.vel4[i];
-            // the full sums at the final h (partner data from global memory,
-            // the loads of U entries issued together)
-            zero();
-            for (int t0 = 0; t0 < nmax; t0 += UF * S) {
-                V4<T> sj[UF], pj[UF], vj[UF];
-                bool in[UF];
-    #pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    const int e = t0 + u * S + js;
-                    const bool ok = e < nl;
-                    sj[u] = m.s[0][ok ? el[e] : 0];
-                    in[u] = ok && dist2_unfused(pi.x - sj[u].x, pi.y - sj[u].y, pi.z - sj[u].z) < H2;
-                }
-    #pragma unroll
-                for (int u = 0; u < UF; ++u) {
-                    int j = in[u] ? as_int<T>(sj[u].w) : 0;
-                    if (j < 0 || j >= a.n) j = 0;  // cannot happen with a valid list
-                    pj[u] = a.pos4[j];
-                    vj[u] = a.vel4[j];
-                }
-    #pragma unroll
-                for (int u = 0; u < UF; ++u)
-                    if (in[u]) body(sj[u], pj[u], vj[u]);
-            }
-            evals += nl;
             // tests: the list pass plus every list evaluation
             tested_lane += lead ? (unsigned long long)evals : 0ull;
         } else {
