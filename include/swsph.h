@@ -89,6 +89,19 @@ typedef enum swsph_dtype { SWSPH_F32 = 0, SWSPH_F64 = 1 } swsph_dtype;
 #define SWSPH_PER_TASK_LAUNCH  0x4u  /* one kernel launch per tile task */
 #define SWSPH_FLAT_LAUNCH      0x8u  /* one launch, one wavefront per task, no queue */
 #define SWSPH_TIMING           0x10u /* record HIP events around every loop-kernel launch */
+/* swsph_step only: the density, gradient and force loops of every box in one
+ * persistent launch.  Its task queue holds every density tile, then every
+ * gradient/force tile box by box; a gradient/force tile starts once all
+ * density tiles of its box are done (a per-box phase counter), with task
+ * lists built once beforehand, before h is known, at the density margin
+ * over the guessed supports (a superset of what the force loop needs
+ * wherever no h ends beyond that margin over its guess).  Boxes where some
+ * h did (and tiles whose support outgrew their list) are finished after the
+ * launch by the separate-launch path: density fix-up passes, lists at the
+ * final h, the gradient/force loop.  Results agree with the default path
+ * to rounding (sums in another order), neighbour counts exactly.  Meant for
+ * many independent boxes with usable h guesses (Sec. 4 fine-graining). */
+#define SWSPH_SINGLE_LAUNCH    0x20u
 
 /* Scheme constants and execution options.  swsph_config_default() fills
  * eta = 1.2348, eps = 2, gamma = 5/3, alpha = 1, beta = 3, h_tol = 2e-6,
@@ -181,7 +194,9 @@ typedef struct swsph_stats {
     uint64_t n_tiles_dens;       /* density tile tasks of the last bin */
     uint64_t dens_listed;        /* density tile passes that swept per-particle neighbour
                                     lists (the others re-test the staged set every sweep) */
-    uint64_t reserved[4];
+    uint64_t single_redo;        /* SWSPH_SINGLE_LAUNCH step: gradient/force tiles left to
+                                    the separate-launch path */
+    uint64_t reserved[3];
 } swsph_stats;
 
 typedef struct swsph_plan swsph_plan;

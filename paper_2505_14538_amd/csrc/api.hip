@@ -153,6 +153,10 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.cands = take(4 * (uint64_t)G.cand_cap);
     l.trad = take(4 * (uint64_t)toff);
     l.tflag = take(4 * (uint64_t)toff);
+    l.trad_d = take(4 * (uint64_t)toff);
+    l.fredo = take(4 * (uint64_t)toff);
+    l.forder = take(4 * 2 * (uint64_t)toff);
+    l.boxph = take(4 * (32 + 2) * (uint64_t)n_box);  // phase words a cache line apart
     l.d_out = take(10 * T * N);
     l.d_int = take(2 * 4 * N);
     l.g_out = take(3 * T * N);
@@ -315,6 +319,10 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.build_waves = pl->G.build_waves;
     b.trad = (float*)(w + l.trad);
     b.tflag = (int32_t*)(w + l.tflag);
+    b.trad_d = (float*)(w + l.trad_d);
+    b.fredo = (int32_t*)(w + l.fredo);
+    b.forder = (int32_t*)(w + l.forder);
+    b.boxph = (uint32_t*)(w + l.boxph);
     b.d_out = w + l.d_out;
     b.d_int = (int32_t*)(w + l.d_int);
     b.g_out = w + l.g_out;
@@ -544,18 +552,10 @@ namespace {
 // gathered into binned order, the task lists built, and one loop kernel
 // computes both loops (the outputs asked for are copied out), so the
 // separate calls and the joint one give the same bits.
+// The binned gradient and force results back to the caller's order.
 template <typename T>
-int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
-               swsph_gradient_out* go, swsph_force_out* fo, void* ws, hipStream_t s) {
-    BinPtrs b = ptrs_of(pl, ws);
-    Scheme sc = scheme_of(pl);
-    const int mode = mode_of(pl);
+void gf_unsort(const BinPtrs& b, swsph_gradient_out* go, swsph_force_out* fo, hipStream_t s) {
     const int64_t n = b.n;
-    (void)p;
-    launch_prep_dens<T>(b, sc, d, s);
-    launch_gf_tasks<T>(b, sc, s);
-    if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
-        return fail(SWSPH_E_HIP, "gradient/force kernel launch failed");
     UnsortSet u{};
     if (go) {
         u.in[u.k] = (T*)b.g_out;
@@ -572,7 +572,57 @@ int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out
         if (fo->nint) launch_unsort<int32_t>(n, b.rank, b.f_int, fo->nint, s);
     }
     launch_unsort_multi<T>(n, b.rank, u, s);
+}
+
+template <typename T>
+int gf_enqueue(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+               swsph_gradient_out* go, swsph_force_out* fo, void* ws, hipStream_t s) {
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    const int mode = mode_of(pl);
+    (void)p;
+    launch_prep_dens<T>(b, sc, d, s);
+    launch_gf_tasks<T>(b, sc, s);
+    if (launch_force<T>(b, sc, mode, pl->lds_cap, s))
+        return fail(SWSPH_E_HIP, "gradient/force kernel launch failed");
+    gf_unsort<T>(b, go, fo, s);
     return hip_check(hipGetLastError(), go ? (fo ? "gradient+force" : "gradient") : "force");
+}
+
+// The single-launch step after the bin: density, gradient and force loops
+// of every box in one launch (and the separate-launch path for what it
+// leaves), then the results in the caller's order.
+template <typename T>
+int single_enqueue(swsph_plan* pl, swsph_density_out* d, swsph_gradient_out* go,
+                   swsph_force_out* fo, void* ws, hipStream_t s) {
+    BinPtrs b = ptrs_of(pl, ws);
+    Scheme sc = scheme_of(pl);
+    if (launch_single<T>(b, sc, pl->lds_cap_d, pl->lds_cap, s))
+        return fail(SWSPH_E_HIP, "single-launch loop kernel launch failed");
+    unsort_density<T>(b, d, s);
+    gf_unsort<T>(b, go, fo, s);
+    return hip_check(hipGetLastError(), "single-launch step");
+}
+
+// Whether swsph_step takes the single launch: asked for, both gradient/force
+// outputs wanted, and density tiles smaller than gradient/force tiles (they
+// stage from their gradient/force tile's list).
+bool single_launch(const swsph_plan* pl, const swsph_gradient_out* go, const swsph_force_out* fo) {
+    return (pl->cfg.flags & SWSPH_SINGLE_LAUNCH) && !(pl->cfg.flags & SWSPH_PER_TASK_LAUNCH) &&
+           (go || fo) && pl->tile_d < pl->tile;
+}
+
+int single_checked(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
+                   swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
+    int r = check_particles(pl, p, true);
+    if (r) return r;
+    if (!d || (p->n > 0 && (!d->h || !d->rho || !d->f)))
+        return fail(SWSPH_E_ARG, "density output needs h, rho and f");
+    r = check_bound(pl, p, ws);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    return pl->cfg.dtype == SWSPH_F64 ? single_enqueue<double>(pl, d, go, fo, ws, s)
+                                      : single_enqueue<float>(pl, d, go, fo, ws, s);
 }
 
 int gf_checked(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
@@ -753,6 +803,7 @@ int swsph_read_stats(swsph_plan* pl, const void* ws, swsph_stats* out, void* str
     out->restages = c.restages;
     out->n_tiles_dens = c.n_tiles_d;
     out->dens_listed = c.dens_listed;
+    out->single_redo = c.single_redo;
     if (c.status & SWSPH_ST_DOMAIN) return fail(SWSPH_E_DOMAIN, "a particle lies outside its box");
     if (c.status & SWSPH_ST_REACH) return fail(SWSPH_E_REACH, "a support radius reaches half a box");
     if (c.status & SWSPH_ST_CAPACITY) return fail(SWSPH_E_CAPACITY, "internal capacity exceeded");
@@ -810,6 +861,7 @@ int step_eager(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
                swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
     int r = swsph_bin(pl, p, ws, stream);
     if (r) return r;
+    if (single_launch(pl, go, fo)) return single_checked(pl, p, d, go, fo, ws, stream);
     r = swsph_density(pl, p, d, ws, stream);
     if (r) return r;
     if (go || fo) return gf_checked(pl, p, d, go, fo, ws, stream);
@@ -851,8 +903,13 @@ int swsph_step(swsph_plan* pl, const swsph_particles* p, swsph_density_out* d,
         r = hip_check(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal), "begin capture");
         if (r) return r;
         bin_enqueue(pl, p, pl->cap);
-        int rr = swsph_density(pl, p, d, ws, pl->cap);
-        if (!rr && (go || fo)) rr = gf_checked(pl, p, d, go, fo, ws, pl->cap);
+        int rr = 0;
+        if (single_launch(pl, go, fo)) {
+            rr = single_checked(pl, p, d, go, fo, ws, pl->cap);
+        } else {
+            rr = swsph_density(pl, p, d, ws, pl->cap);
+            if (!rr && (go || fo)) rr = gf_checked(pl, p, d, go, fo, ws, pl->cap);
+        }
         hipGraph_t g = nullptr;
         r = hip_check(hipStreamEndCapture(pl->cap, &g), "end capture");
         if (!r && rr) r = rr;

@@ -47,6 +47,12 @@ struct BinPtrs {
     int64_t build_waves;       // most task-build wavefronts (the capacity counts one window each)
     float* trad;
     int32_t* tflag;
+    float* trad_d;             // single-launch step: density fix-up radii
+    int32_t* fredo;            // single-launch step: gradient/force tiles to redo
+    int32_t* forder;           // single-launch step: the launch's task order
+    uint32_t* boxph;           // single-launch step: per box, done count | redo bit
+                               // (32 words apart); then the density tiles of each box;
+                               // then each box's smallest gradient/force list radius
     void *d_out, *g_out, *f_out, *adj;
     int32_t *d_int, *f_int;
     int64_t n;
@@ -100,7 +106,9 @@ void launch_unsort_multi(int64_t n, const int32_t* rank, const UnsortSet& set, h
 template <typename T>
 void launch_sortcopy(int64_t n, const int32_t* perm, const void* in, void* out, hipStream_t s);
 
-// tasks.hip: mode 0 density, 1 gradient, 2 force; fixup: only flagged tiles
+// tasks.hip: mode 0 density, 1 gradient, 2 force, 3 force at the density
+// margin over the guessed supports (single-launch step); fixup: only the
+// listed tiles (density: flagged for a fix-up; force: to redo)
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s);
 void launch_order(const BinPtrs& b, hipStream_t s);
@@ -129,6 +137,12 @@ template <typename T>
 int launch_switch_loops(const BinPtrs& b, const Scheme& sc, const SwitchConsts& sw,
                         const swsph_density_out* d, const swsph_switch_state* st, int mode,
                         int lds_cap, hipStream_t s);
+// The single-launch step's loops (after the bin): lists at the margin over
+// the guessed supports, one launch for every box's density, gradient and
+// force tiles, then the separate-launch path for what it left (the binned
+// outputs as after launch_density and launch_force).
+template <typename T>
+int launch_single(const BinPtrs& b, const Scheme& sc, int lds_cap_d, int lds_cap, hipStream_t s);
 template <typename T>
 int launch_backward(const BinPtrs& b, const Scheme& sc, const swsph_force_grad* g,
                     const swsph_density_out* d, int lds_cap, hipStream_t s);

@@ -52,14 +52,19 @@ __device__ __forceinline__ double step_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float step_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double step_exp(double x) { return exp(x); }
 
-template <typename T, int CAP>
-__device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, WaveStats& ws) {
+// SINGLE (the single-launch step): also write (rho, f, c, A) of each
+// particle, and return 1 when some h needs a wider staged set, 2 when an
+// iteration failed or some h has a support the box's early gradient/force
+// lists may not cover (0 otherwise).
+template <typename T, int CAP, bool SINGLE = false>
+__device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t,
+                                            WaveStats& ws, float Rset = 0.f) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
     tl.box = uniform(tl.box);
-    if (tl.count <= 0) return;
-    if (a.fixup && a.tflag[t] == 0) return;
+    if (tl.count <= 0) return 0;
+    if (a.fixup && a.tflag[t] == 0) return 0;
     const int lane = lane_id();
     const GroupMap q = group_map(tl.count);
     const int js = q.js, S = q.S, c = q.c;
@@ -92,6 +97,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
             Rf = Rcf;
         }
         if (!(Rf > 0.f)) Rf = Rcf;
+        if (SINGLE && Rset > Rf) Rf = Rset;  // a second run with a wider radius
         R = (T)Rf;
     } else {
         R = (T)a.trad[t];
@@ -225,6 +231,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
     bool listed = flushes == 0;
     // Everything after the staging: lists or re-tested sweeps, the Newton
     // iteration, the outputs.
+    int redo = 0;
     auto density_sweeps = [&]() {
         // Neighbour lists, per i-slot in staged order: the staged candidates
         // within R of the slot's particle (fixed h: within its support, which
@@ -399,6 +406,7 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
         if (pend && last) { failed = true; pend = false; }
         if (!conv && !pend && act) failed = true;
         // outputs (sorted order): h rho rho_dh wcount wcount_dh div cx cy cz f | nngb iters
+        bool beyond = false;
         if (lead) {
             // reciprocals (the hardware's in FP32, within an ulp) instead of
             // divisions
@@ -424,6 +432,18 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
             a.iout[0 * n + i] = cnt - 1;
             a.iout[1 * n + i] = failed ? -iters : iters;
             a.hs[i] = pend ? want : h;
+            if constexpr (SINGLE) {
+                const T gm1 = a.gamma - (T)1;
+                const T u = vi.w;
+                const T fi = o[9 * n + i];
+                a.dens4_out[i] = V4<T>{rho, fi, sqrt(a.gamma * gm1 * u), fi * gm1 * u / rho};
+                // a support beyond the margin over the guess and beyond the
+                // box's smallest list radius
+                const T rmin = (T)__uint_as_float(a.boxph[(BOX_STRIDE + 1) * a.n_box + tl.box]);
+                const T hh = h * ((T)1 + (T)1e-5);
+                beyond = !fixed && !pend &&
+                         (failed || (hh > a.hguess[i] * a.dmargin && eps * hh > rmin));
+            }
         }
         const unsigned long long pmask = ballot(pend);
         const unsigned long long fmask = ballot(failed && js == 0);
@@ -448,9 +468,11 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
         ws.lane_smax = max(ws.lane_smax, iters);
         ws.sweeps += (unsigned long long)(iters - iters0);
         ws.failed += (unsigned long long)__popcll(fmask);
+        if constexpr (SINGLE) redo = (pmask != 0ull ? 1 : 0) | (ballot(beyond) != 0ull ? 2 : 0);
     };
     density_sweeps();
     ws.listed += listed ? 1ull : 0ull;
+    return redo;
 }
 
 // ------------------------------------------------- gradient and force tile
@@ -460,8 +482,11 @@ __device__ void density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t, Wa
 // outputs do not feed the force loop (alpha is constant, and the pairwise
 // signal speed enters Eq. 9), so nothing orders the two.
 
-template <typename T, int CAP>
-__device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, WaveStats& ws) {
+// SINGLE: stage with radius Rown instead of the task build's (the
+// single-launch step's lists were built with a larger one).
+template <typename T, int CAP, bool SINGLE = false>
+__device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t,
+                                           WaveStats& ws, float Rown = 0.f) {
     Tile tl = a.tiles[t];
     tl.begin = uniform(tl.begin);
     tl.count = uniform(tl.count);
@@ -483,7 +508,7 @@ __device__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t, Wave
     const T H = mul_unfused(eps, h);
     const T H2 = act ? mul_unfused(H, H) : (T)-1;
     const T invH = (T)1 / H;
-    const T R = (T)a.trad[t];
+    const T R = (T)(SINGLE ? Rown : a.trad[t]);
     const T cn = (T)(8.0 / PI_D);
     const T kgi = cn * invH * invH * invH * invH;
     const T rhoi = di.x, fi = di.y, ci = di.z, Ai = di.w;
@@ -840,10 +865,37 @@ __global__ void k_fix_list(const int32_t* __restrict__ tflag,
     }
 }
 
-// Density: the first pass, then up to DENS_FIXUPS fix-up passes for tiles
-// whose Newton iteration needed a wider task list (the last pass latches
-// failures).
+// Density fix-up passes over the tiles a first pass flagged (b.tflag, their
+// wider radii in b.trad): each builds their lists and reruns them (any
+// order); the last latches failures.
 constexpr int DENS_FIXUPS = 3;
+template <typename T>
+static int density_fixups(const BinPtrs& b, const Scheme& sc, KArgs<T> a, int mode,
+                          hipStream_t s) {
+    a.order = b.tmpidx;
+    a.ntask = &b.cnt->n_fix;
+    a.xcd_split = 0;
+    a.parent = nullptr;
+    a.boxph = nullptr;
+    int r = 0;
+    for (int pass = 1; pass <= DENS_FIXUPS && !r; ++pass) {
+        launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
+        hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
+                           (const int32_t*)b.tflag, (const unsigned long long*)b.ntiles, b.cnt,
+                           b.tmpidx);
+        launch_tasks<T>(b, sc, 0, true, s);
+        a.fixup = pass == DENS_FIXUPS ? 2 : 1;
+        timer_begin(sc.timer, 0, s);
+        // fix-up tiles are few and their lists long: the largest staging
+        // buffer keeps them in LDS across their sweeps
+        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, 1024, 0, s);
+        timer_end(sc.timer, 0, s);
+    }
+    return r;
+}
+
+// Density: the first pass, then the fix-up passes for tiles whose Newton
+// iteration needed a wider task list.
 template <typename T>
 int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, hipStream_t s) {
     const BinPtrs b = density_view(bin);
@@ -864,24 +916,7 @@ int launch_density(const BinPtrs& bin, const Scheme& sc, int mode, int lds_cap, 
     int r = launch_loop<L_DENS, T>(a, mode, lds_cap, 0, s);
     timer_end(sc.timer, 0, s);
     if (r || (sc.flags & SWSPH_FIXED_H)) return r;
-    // fix-up passes run over the list of flagged tiles only (any order)
-    a.order = b.tmpidx;
-    a.ntask = &b.cnt->n_fix;
-    a.xcd_split = 0;
-    for (int pass = 1; pass <= DENS_FIXUPS && !r; ++pass) {
-        launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
-        hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
-                           (const int32_t*)b.tflag, (const unsigned long long*)b.ntiles, b.cnt,
-                           b.tmpidx);
-        launch_tasks<T>(b, sc, 0, true, s);
-        a.fixup = pass == DENS_FIXUPS ? 2 : 1;
-        timer_begin(sc.timer, 0, s);
-        // fix-up tiles are few and their lists long: the largest staging
-        // buffer keeps them in LDS across their sweeps
-        r = launch_loop<L_DENS, T>(a, mode == MODE_PER_TASK ? MODE_FLAT : mode, 1024, 0, s);
-        timer_end(sc.timer, 0, s);
-    }
-    return r;
+    return density_fixups<T>(b, sc, a, mode, s);
 }
 // Task lists of the joint gradient/force loop: the force list (support
 // max(H_i, H_j)) contains every pair the gradient loop needs (support H_i).
@@ -908,6 +943,373 @@ template void launch_gf_tasks<float>(const BinPtrs&, const Scheme&, hipStream_t)
 template void launch_gf_tasks<double>(const BinPtrs&, const Scheme&, hipStream_t);
 template int launch_force<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 template int launch_force<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+
+// ------------------------------------------------------ single launch
+// Every box's density, gradient and force tiles in one persistent launch
+// (Sec. 4: one kernel for many small, uneven tasks instead of a launch per
+// task or per loop).  Each of the queue's XCD segments holds its share of
+// the density tiles, then its share of the gradient/force tiles, both box
+// by box.  A gradient/force tile first waits until its box's phase word
+// counts all of the box's density tiles as done.  Density tiles wait for
+// nothing, and a wavefront reaches a segment's gradient/force tiles only
+// after every density tile of that segment has been popped; each segment is
+// worked on by the wavefronts of its own XCD from the start, so every density
+// tile waited for gets done (the grid never exceeds the co-resident
+// workgroups either).  The wait is capped: a timeout latches LOOPCAP and
+// leaves the box to the redo path.  The
+// gradient/force lists were built before the launch at the density margin
+// over the guessed supports; a tile runs on them when its box's h all ended
+// within that margin (its density tiles set the redo bit otherwise) and its
+// own radius at the final h fits its list's; the rest is redone afterwards.
+constexpr int BOX_SPIN_MAX = 1 << 16;  // polls about 2 us apart: 0.1 s at most
+
+// Density tiles of every box (the totals the phase words count up to):
+// tiles come box by box, so each box's are a range found by binary search.
+__global__ void k_box_tiles(const Tile* __restrict__ tiles_d, const unsigned long long* __restrict__ ntd,
+                            int32_t n_box, uint32_t* __restrict__ total) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_box) return;
+    const int64_t nt = (int64_t)*ntd;
+    auto first = [&](int box) {  // first tile of a box >= box
+        int64_t lo = 0, hi = nt;
+        for (int it = 0; it < 64 && lo < hi; ++it) {
+            const int64_t mid = (lo + hi) / 2;
+            if (tiles_d[mid].box < box) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    total[b] = (uint32_t)(first(b + 1) - first(b));
+}
+
+// Smallest task-list radius of every box's gradient/force tiles (positive
+// floats order as their bit patterns).
+__global__ void k_box_rmin(const Tile* __restrict__ tiles, const unsigned long long* __restrict__ ntiles,
+                           const float* __restrict__ trad, int32_t n_box, uint32_t* __restrict__ rmin) {
+    const int64_t nt = (int64_t)*ntiles;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += nth) {
+        int box = -1;
+        float r = 3.0e38f;
+        if (t < nt) {
+            const Tile tl = tiles[t];
+            if (tl.count > 0 && tl.box >= 0 && tl.box < n_box && trad[t] > 0.f) {
+                box = tl.box;
+                r = trad[t];
+            }
+        }
+        // consecutive tiles mostly share a box: one atomic per wavefront then
+        const int b0 = __shfl(box, 0, WAVE);
+        if (ballot(box != b0) == 0ull) {
+            const float m = wave_min(r);
+            if (lane_id() == 0 && b0 >= 0) atomicMin(&rmin[b0], __float_as_uint(m));
+        } else if (box >= 0) {
+            atomicMin(&rmin[box], __float_as_uint(r));
+        }
+    }
+}
+
+// The launch's queue, cut (as the queue cuts any list) into NXCD segments
+// [B_x, B_x+1), B_x = nt x / NXCD: segment x holds density tiles D_x ..
+// D_x+1 - 1, D_x = B_x nd / nt, then gradient/force tiles (as nd + t) from
+// B_x - D_x on -- both counts rise with x, so the lists stay in their order,
+// box by box, and every segment has its density tiles first.
+__global__ void k_single_order(const int32_t* __restrict__ order_d,
+                               const unsigned long long* __restrict__ ntd,
+                               const int32_t* __restrict__ order_f,
+                               const unsigned long long* __restrict__ ntf,
+                               int32_t* __restrict__ items, unsigned long long* __restrict__ nitems) {
+    const int64_t nd = (int64_t)*ntd, nf = (int64_t)*ntf, nt = nd + nf;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int64_t k0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k0 == 0) *nitems = (unsigned long long)nt;
+    for (int64_t k = k0; k < nt; k += nth) {
+        int x = 0;
+        while (x + 1 < NXCD && nt * (x + 1) / NXCD <= k) ++x;
+        const int64_t bx = nt * x / NXCD, bx1 = nt * (x + 1) / NXCD;
+        const int64_t dx = bx * nd / nt, dx1 = bx1 * nd / nt;
+        const int64_t j = k - bx;
+        items[k] = j < dx1 - dx ? order_d[dx + j]
+                                : (int32_t)(nd + order_f[(bx - dx) + (j - (dx1 - dx))]);
+    }
+}
+
+// ready: the box this wavefront last found complete (no second wait or
+// acquire for its further tiles).
+template <typename T, int CAP>
+__device__ __forceinline__ void single_force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t,
+                                                  WaveStats& ws, int& ready) {
+    const Tile tl = a.tiles[t];
+    const int count = uniform(tl.count), box = uniform(tl.box);
+    if (count <= 0) return;
+    const int lane = lane_id();
+    if (box != ready) {
+    uint32_t w = BOX_REDO;
+    if (lane == 0) {
+        const uint32_t need = a.boxph[BOX_STRIDE * a.n_box + box];
+        int it = 0;
+        for (; it < BOX_SPIN_MAX; ++it) {
+            const uint32_t v = __hip_atomic_load(&a.boxph[box * BOX_STRIDE], __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            // a box already sent to the redo path needs no waiting
+            if ((v & BOX_DONE) >= need || (v & BOX_REDO)) {
+                w = v;
+                break;
+            }
+            // poll gently: thousands of waiting wavefronts on a few words
+            // would otherwise crowd the cache channel that holds them
+            __builtin_amdgcn_s_sleep(64);
+        }
+        if (it == BOX_SPIN_MAX) {
+            // cannot happen with the queue order above; the box is redone
+            // (and later waits on it end at once)
+            latch(a.cnt, SWSPH_ST_LOOPCAP);
+            atomicOr(&a.boxph[box * BOX_STRIDE], BOX_REDO);
+        }
+    }
+    w = (uint32_t)__shfl((int)w, 0, WAVE);
+    // acquire: the box's density results (one cache invalidation per box
+    // and wavefront: across XCDs this is costly)
+    __threadfence();
+    if (w & BOX_REDO) return;  // the redo path takes the whole box
+    ready = box;
+    } else if (a.boxph[box * BOX_STRIDE] & BOX_REDO) {
+        return;
+    }
+    const int begin = uniform(tl.begin);
+    const T hi = lane < count ? a.hs[begin + lane] : (T)0;
+    const T hmax = wave_max(hi);
+    // the radius a task build at the final h would give the tile
+    const float L = (float)a.boxtab[box].L;
+    const float R = (float)(a.eps * hmax * (T)(1 + 4e-7));
+    if (!(R < 0.5f * L * (1.0f - 1e-6f)) || !(R <= a.trad[t]) || !(R > 0.f)) {
+        if (lane == 0) a.fredo[t] = 1;
+        return;
+    }
+    force_tile<T, CAP, true>(m, a, t, ws, R);
+}
+
+template <typename T, int CAPD, int CAPF>
+__global__ void __launch_bounds__(WPB * WAVE) SWSPH_WAVES_PER_EU(sizeof(T) != 4 ? 1 : 3)
+k_single(KArgs<T> ad, KArgs<T> af, KArgs<T> aq) {
+    SWSPH_DYN_SHARED char smem[];
+    constexpr size_t WMD = sizeof(WaveMem<T, CAPD, 1>), WMF = sizeof(WaveMem<T, CAPF, 4>);
+    constexpr size_t WMS = WMD > WMF ? WMD : WMF;
+    const int wave = threadIdx.x / WAVE;
+    char* wm = smem + wave * WMS;
+    const int64_t nd = (int64_t)*ad.ntask;
+    WaveStats wsd, wsf;
+    // density tiles done by this wavefront, not yet counted: box, count,
+    // redo.  They are released together (one fence) when the box changes,
+    // before the first gradient/force tile and at the end: a wavefront never
+    // waits while it holds uncounted tiles, so every wait still ends.
+    int sbox = -1, ready = -1;
+    uint32_t scnt = 0;
+    bool sredo = false;
+    auto release = [&]() {
+        if (sbox < 0) return;
+        __threadfence();
+        if (lane_id() == 0) {
+            if (sredo) atomicOr(&ad.boxph[sbox * BOX_STRIDE], BOX_REDO);
+            atomicAdd(&ad.boxph[sbox * BOX_STRIDE], scnt);
+        }
+        sbox = -1;
+        scnt = 0;
+        sredo = false;
+    };
+    for_each_task(aq, MODE_QUEUE, [&](int k) {
+        if (k < nd) {
+            const Tile tl = ad.tiles[k];
+            const int box = uniform(tl.box);
+            if (box != sbox) release();
+            sbox = box;
+            auto& md = *(WaveMem<T, CAPD, 1>*)wm;
+            int code = density_tile<T, CAPD, true>(md, ad, k, wsd);
+            if (code == 1) {
+                // an h needs a wider staged set: the tile's h (the converged
+                // ones, and the wider guesses the others asked for) are in
+                // hs; run it again at once when its gradient/force tile's
+                // list covers the wider radius (the fix-up path otherwise)
+                const int count = uniform(tl.count), begin = uniform(tl.begin);
+                const T hm = wave_max(lane_id() < count ? ad.hs[begin + lane_id()] : (T)0);
+                const float Rn = (float)(ad.eps * hm * (T)1.0625);
+                const float Rp = af.trad[uniform(ad.parent[k])];
+                if (Rn <= Rp) code = density_tile<T, CAPD, true>(md, ad, k, wsd, Rp);
+            }
+            sredo = sredo || code != 0;
+            ++scnt;
+        } else {
+            release();
+            single_force_tile<T, CAPF>(*(WaveMem<T, CAPF, 4>*)wm, af, (int)(k - nd), wsf, ready);
+        }
+    });
+    release();
+    wsd.flush(ad.cnt, LOOP_DENSITY, false);
+    wsf.flush(af.cnt, LOOP_FORCE, true);
+}
+
+// Gradient/force tiles the single launch left: flagged by the tile, or in a
+// box with the redo bit.  fredo[t] becomes the flag, the list goes to tmpidx.
+__global__ void k_redo_list(const Tile* __restrict__ tiles, const unsigned long long* __restrict__ ntiles,
+                            const uint32_t* __restrict__ boxph, int32_t n_box,
+                            int32_t* __restrict__ fredo, Counters* __restrict__ cnt,
+                            int32_t* __restrict__ list) {
+    const int64_t nt = (int64_t)*ntiles;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nt; base += nth) {
+        const int64_t t = base + threadIdx.x;
+        bool f = false;
+        if (t < nt) {
+            const int b = tiles[t].box;
+            f = fredo[t] != 0 || (b >= 0 && b < n_box && (boxph[b * BOX_STRIDE] & BOX_REDO) != 0u);
+            fredo[t] = f ? 1 : 0;
+        }
+        const unsigned long long m = ballot(f);
+        int at = 0;
+        if (lane_id() == 0 && m) {
+            at = (int)atomicAdd(&cnt->n_fix, (unsigned long long)__popcll(m));
+            atomicAdd(&cnt->single_redo, (unsigned long long)__popcll(m));
+        }
+        at = __shfl(at, 0, WAVE);
+        if (f) list[at + mbcnt(m)] = (int32_t)t;
+    }
+}
+
+// (rho, f, c, A) of every binned particle from the binned density results.
+template <typename T>
+__global__ void k_dens4_binned(int64_t n, const T* __restrict__ dout,
+                               const V4<T>* __restrict__ vel4, T gamma,
+                               V4<T>* __restrict__ dens4) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const T rho = dout[1 * n + s], f = dout[9 * n + s], u = vel4[s].w;
+    const T gm1 = gamma - (T)1;
+    dens4[s] = V4<T>{rho, f, sqrt(gamma * gm1 * u), f * gm1 * u / rho};
+}
+
+template <typename T>
+__global__ void k_copy_n(int64_t n, const T* __restrict__ in, T* __restrict__ out) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s < n) out[s] = in[s];
+}
+
+template <typename T, int CAPD, int CAPF>
+static int launch_single_cap(const KArgs<T>& ad, const KArgs<T>& af, const KArgs<T>& aq,
+                             hipStream_t s) {
+    void (*kern)(KArgs<T>, KArgs<T>, KArgs<T>) = k_single<T, CAPD, CAPF>;
+    constexpr size_t WMD = sizeof(WaveMem<T, CAPD, 1>), WMF = sizeof(WaveMem<T, CAPF, 4>);
+    const size_t shm = (WMD > WMF ? WMD : WMF) * WPB;
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm) != hipSuccess)
+            return -1;
+        attr_set = true;
+    }
+    launch_fill_u32(aq.queue, 2 * NXCD, 0u, s);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, WPB * WAVE, shm) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int64_t blocks = (int64_t)per_cu * device_cu_count();
+    const int64_t need = (aq.tile_cap + WPB - 1) / WPB;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WPB * WAVE), shm, s, ad, af, aq);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_single(const BinPtrs& bin, const Scheme& sc, int lds_cap_d, int lds_cap,
+                  hipStream_t s) {
+    if (bin.n <= 0) return 0;
+    const BinPtrs bd = density_view(bin);
+    // gradient/force lists at the margin over the guessed supports; the
+    // density tiles stage from them as from their parent's density list
+    launch_hmax_pyramid<T>(bin, sc, s);
+    launch_tasks<T>(bin, sc, 3, false, s);
+    const int32_t nb = bin.n_box;
+    const unsigned gn = (unsigned)((bin.n + 255) / 256);
+    // the guesses, for the check of each h against them (the third gradient
+    // output array is free in this step)
+    T* hguess = (T*)bin.g_out + 2 * bin.n;
+    hipLaunchKernelGGL(k_copy_n<T>, dim3(gn), dim3(256), 0, s, bin.n, (const T*)bin.hs, hguess);
+    uint32_t* total = bin.boxph + (int64_t)BOX_STRIDE * nb;
+    uint32_t* rmin = total + nb;
+    launch_fill_u32(bin.boxph, (int64_t)BOX_STRIDE * nb, 0u, s);
+    launch_fill_u32(rmin, nb, 0x7f7fffffu, s);  // FLT_MAX
+    launch_fill_u32(bin.fredo, bin.tile_cap, 0u, s);
+    hipLaunchKernelGGL(k_box_tiles, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                       (const Tile*)bd.tiles, (const unsigned long long*)bd.ntiles, nb, total);
+    hipLaunchKernelGGL(k_box_rmin, dim3(wave_grid(bin.tile_cap, 4)), dim3(256), 0, s,
+                       (const Tile*)bin.tiles, (const unsigned long long*)bin.ntiles,
+                       (const float*)bin.trad, nb, rmin);
+    hipLaunchKernelGGL(k_single_order, dim3(wave_grid(2 * bin.tile_cap, 4)), dim3(256), 0, s,
+                       (const int32_t*)bd.order, (const unsigned long long*)bd.ntiles,
+                       (const int32_t*)bin.order, (const unsigned long long*)bin.ntiles,
+                       bin.forder, &bin.cnt->n_items);
+    KArgs<T> ad = make_args<T>(bd, sc);
+    ad.out = (T*)bd.d_out;
+    ad.iout = bd.d_int;
+    ad.parent = bin.dparent;
+    ad.trad = bin.trad_d;  // fix-up radii: the lists' radii stay for the check above
+    ad.dens4_out = (V4<T>*)bin.dens4;
+    ad.hguess = hguess;
+    ad.boxph = bin.boxph;
+    KArgs<T> af = make_args<T>(bin, sc);
+    af.out = (T*)bin.f_out;
+    af.gout = (T*)bin.g_out;
+    af.iout = bin.f_int;
+    af.boxph = bin.boxph;
+    af.fredo = bin.fredo;
+    KArgs<T> aq = ad;
+    aq.order = bin.forder;
+    aq.ntask = &bin.cnt->n_items;
+    aq.tile_cap = 2 * bin.tile_cap;
+    aq.xcd_split = 1;  // per XCD, density tiles first in each segment
+    aq.qchunk = 4;
+    aq.queue = bin.cnt->queue[1];
+    int r;
+    if constexpr (sizeof(T) == 4) {
+        if (lds_cap_d >= 512) r = launch_single_cap<T, 512, 128>(ad, af, aq, s);
+        else if (lds_cap_d >= 256) r = launch_single_cap<T, 256, 128>(ad, af, aq, s);
+        else r = launch_single_cap<T, 128, 128>(ad, af, aq, s);
+    } else {
+        r = launch_single_cap<T, 128, 128>(ad, af, aq, s);
+    }
+    (void)lds_cap;
+    if (r) return r;
+    // what the launch left: density fix-ups (their radii in trad_d), then
+    // the gradient/force tiles of boxes with the redo bit or flagged
+    if (!(sc.flags & SWSPH_FIXED_H)) {
+        BinPtrs bx = bd;
+        bx.trad = bin.trad_d;
+        r = density_fixups<T>(bx, sc, ad, MODE_QUEUE, s);
+        if (r) return r;
+        hipLaunchKernelGGL(k_dens4_binned<T>, dim3(gn), dim3(256), 0, s, bin.n,
+                           (const T*)bin.d_out, (const V4<T>*)bin.vel4, (T)sc.gamma,
+                           (V4<T>*)bin.dens4);
+    }
+    launch_fill_u32(&bin.cnt->n_fix, 2, 0u, s);
+    hipLaunchKernelGGL(k_redo_list, dim3(wave_grid(bin.tile_cap, 4)), dim3(256), 0, s,
+                       (const Tile*)bin.tiles, (const unsigned long long*)bin.ntiles,
+                       (const uint32_t*)bin.boxph, nb, bin.fredo, bin.cnt, bin.tmpidx);
+    launch_hmax_pyramid<T>(bin, sc, s);
+    BinPtrs bf = bin;
+    bf.tflag = bin.fredo;
+    launch_tasks<T>(bf, sc, 2, true, s);
+    KArgs<T> ar = make_args<T>(bin, sc);
+    ar.out = (T*)bin.f_out;
+    ar.gout = (T*)bin.g_out;
+    ar.iout = bin.f_int;
+    ar.order = bin.tmpidx;
+    ar.ntask = &bin.cnt->n_fix;
+    ar.xcd_split = 0;
+    return launch_loop<L_FORCE, T>(ar, MODE_QUEUE, lds_cap, 2, s);
+}
+template int launch_single<float>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
+template int launch_single<double>(const BinPtrs&, const Scheme&, int, int, hipStream_t);
 
 // ------------------------------------------------ time-dependent switches
 

@@ -57,7 +57,31 @@ struct KArgs {
     int32_t h_max_iter;
     uint32_t flags;
     int32_t fixup;             // density: 0 first pass, 1 fix-up pass, 2 last fix-up pass
+    // single-launch step (null otherwise): density tiles also write
+    // (rho, f, c, A) per particle and report to their box's phase word
+    // (checking h against the guesses hguess); gradient/force tiles wait for
+    // it and flag themselves for a redo
+    V4<T>* dens4_out;
+    const T* hguess;
+    uint32_t* boxph;           // per box: done count | BOX_REDO (one cache line each);
+                               // then its density tiles; then its smallest
+                               // gradient/force list radius (float bits)
+    int32_t* fredo;
+    int32_t n_box;
+    int32_t qchunk;            // queue: tasks per pop
 };
+
+constexpr int QCHUNK = 2;  // tasks per queue pop (the loops' default)
+
+// Box phase words sit one cache line apart (their atomics and polls do not
+// share lines); the per-box totals and radii follow them.
+constexpr int BOX_STRIDE = 32;
+
+// Phase word of a box in the single-launch step: density tiles done (low
+// bits) and the redo bit (some h of the box ended beyond the margin its
+// gradient/force lists were built with, or a tile needs a wider search).
+constexpr uint32_t BOX_REDO = 1u << 31;
+constexpr uint32_t BOX_DONE = BOX_REDO - 1u;
 
 // Lane mapping of a tile of c particles (c <= 64): c i-slots times S =
 // floor(64 / c) streams, lane = i-slot + c * stream; the 64 - S c lanes
@@ -488,6 +512,12 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.h_max_iter = sc.h_max_iter;
     a.flags = sc.flags;
     a.fixup = 0;
+    a.dens4_out = nullptr;
+    a.hguess = nullptr;
+    a.boxph = nullptr;
+    a.fredo = nullptr;
+    a.n_box = b.n_box;
+    a.qchunk = QCHUNK;
     return a;
 }
 
@@ -524,7 +554,7 @@ struct WaveStats {
 };
 
 // Task dispatch inside a loop kernel.
-//  * queue: every wavefront pops QCHUNK consecutive tasks at a time until the
+//  * queue: every wavefront pops qchunk consecutive tasks at a time until the
 //    list is drained (at most tile_cap + 1 pops per list).  With xcd_split
 //    the list (in Morton order) is cut into NXCD contiguous segments and a
 //    wavefront starts on the segment of the XCD it runs on (hardware XCC
@@ -532,7 +562,6 @@ struct WaveStats {
 //    wavefront whose segment is drained helps the next ones.
 //  * flat: the static round-robin schedule.
 //  * per-task: the one task of the launch.
-constexpr int QCHUNK = 2;
 constexpr int NXCD = 8;
 
 // One call site of `run` (the tile body is inlined once): the loop keeps a
@@ -544,6 +573,7 @@ __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&&
     const int wave = threadIdx.x / WAVE;
     const int64_t nt = (int64_t)*a.ntask;
     const bool queue = mode == MODE_QUEUE;
+    const int qc = a.qchunk > 0 ? a.qchunk : QCHUNK;
     const bool split = queue && a.xcd_split;
     const int nseg = split ? NXCD : 1;
     const int x0 = split ? xcc_id() % NXCD : 0;
@@ -565,7 +595,7 @@ __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&&
                 const int64_t e = split ? nt * (x + 1) / NXCD : nt;
                 unsigned long long* head = &a.queue[split ? x : 0];
                 int t0 = pv;
-                if (!pre && lane_id() == 0) t0 = (int)atomicAdd(head, (unsigned long long)QCHUNK);
+                if (!pre && lane_id() == 0) t0 = (int)atomicAdd(head, (unsigned long long)qc);
                 pre = false;
                 const int64_t s0 = b + uniform(t0);
                 if (s0 >= e || ++pops > a.tile_cap + 1) {
@@ -574,9 +604,9 @@ __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&&
                     continue;
                 }
                 next = s0;
-                end = min(s0 + QCHUNK, e);
+                end = min(s0 + qc, e);
                 // the next pop goes out now; its latency hides behind these tasks
-                if (lane_id() == 0) pv = (int)atomicAdd(head, (unsigned long long)QCHUNK);
+                if (lane_id() == 0) pv = (int)atomicAdd(head, (unsigned long long)qc);
                 pre = true;
             } else if (mode == MODE_FLAT) {
                 if (flat >= nt) break;

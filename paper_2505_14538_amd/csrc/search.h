@@ -116,10 +116,13 @@ __device__ inline void search_init(SearchMem& m, SearchState& st, const BoxInfo&
 
 // Fill the leaf buffer (at most LEAFCAP) or finish.  Returns true when the
 // search is done (queue empty, or the chunk cap was reached).
+// CELL_H: a cell also stays while its largest support (times hm) reaches
+// the tile.
 template <bool CELL_H>
 __device__ inline bool search_step(SearchMem& m, SearchState& st, const BoxInfo& bi,
                                    const TileGeom& g, float R2, const int32_t* __restrict__ cstart,
-                                   const float* __restrict__ hpyr, int leaf_max, Counters* cnt) {
+                                   const float* __restrict__ hpyr, float hm, int leaf_max,
+                                   Counters* cnt) {
     const int lane = lane_id();
     const float L = (float)bi.L;
     const float pad = 1.0f + 1.0e-4f;
@@ -163,7 +166,7 @@ __device__ inline bool search_step(SearchMem& m, SearchState& st, const BoxInfo&
                 }
                 float crit = R2 * pad;
                 if (CELL_H) {
-                    const float hc = hpyr[bi.pyr_off + pyr_level_off(level) + mort];
+                    const float hc = hpyr[bi.pyr_off + pyr_level_off(level) + mort] * hm;
                     crit = fmaxf(crit, hc * hc * pad);
                 }
                 if (gap2 < crit) {

@@ -66,7 +66,9 @@ struct Counters {
     unsigned long long n_fix;          // tiles listed for the current density fix-up pass
     unsigned long long cand_used;      // task-list entries taken by the current build
     unsigned long long dens_listed;    // density tiles that swept per-particle neighbour lists
-    unsigned long long reserved[4];
+    unsigned long long n_items;        // single-launch step: density plus gradient/force tiles
+    unsigned long long single_redo;    // single-launch step: gradient/force tiles redone after it
+    unsigned long long reserved[3];
 };
 
 enum Loop { LOOP_DENSITY = 0, LOOP_GRADIENT = 1, LOOP_FORCE = 2, LOOP_BACKWARD = 3 };
@@ -80,6 +82,9 @@ struct Layout {
     uint64_t tiles, order, tiles_d, order_d, dparent, ord_table, ord_base;
     // task lists (candidate entries per tile) and density fix-up state
     uint64_t cand_cnt, cand_off, cands, trad, tflag;
+    // single-launch step: density fix-up radii, gradient/force tiles to
+    // redo, the launch's task order, per-box phase words and tile totals
+    uint64_t trad_d, fredo, forder, boxph;
     // sorted-order results
     uint64_t d_out;     // 10 arrays of T: h rho rho_dh wcount wcount_dh div cx cy cz f
     uint64_t d_int;     // 2 arrays of int32: nngb iters

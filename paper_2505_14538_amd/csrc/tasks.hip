@@ -32,7 +32,8 @@ struct TArgs {
     const int32_t* tflag;
     Counters* cnt;
     T eps;
-    T margin;
+    T margin;   // on the tile's radius eps * hmax
+    T hmargin;  // force: on every particle's support H_j (and the cell maxima)
     int32_t leaf_max;
     const V4<T>* pos4;
     int64_t n;
@@ -155,7 +156,7 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
         R = (float)(a.eps * hmax * a.margin * (T)(1 + 4e-7));
         if (!(R < Rcap)) {
             // fixed supports (every loop but the Newton density search) must fit
-            if ((MODE != 0 || a.margin == (T)1) && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
+            if (a.margin == (T)1 && lane == 0) latch(a.cnt, SWSPH_ST_REACH);
             R = Rcap;
         }
         if (!(R > 0.f)) R = Rcap;
@@ -165,7 +166,8 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
 #pragma unroll
     for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
     float Rstart = R;
-    if (MODE == 2) Rstart = fmaxf(R, a.hpyr[bi.pyr_off]);
+    const float hm = (float)a.hmargin;
+    if (MODE == 2) Rstart = fmaxf(R, a.hpyr[bi.pyr_off] * hm);
     const float R2 = R * R;
     const T Rt = (T)R;
     const T R2t = Rt * Rt;  // the loops cull with the same value
@@ -177,7 +179,7 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
         search_init(m.sm, st, bi, g, Rstart);
         int64_t total = 0;
         for (int guard = 0; guard < SEARCH_MAX_CHUNKS; ++guard) {
-            const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr,
+            const bool done = search_step<MODE == 2>(m.sm, st, bi, g, R2, a.cstart, a.hpyr, hm,
                                                      a.leaf_max, a.cnt);
             if (st.nleaf > 0) {
                 // prefix sums of the batch's particle counts (two lanes' worth each)
@@ -208,7 +210,7 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
                             const T d2 = dist2_unfused(gx, gy, gz);
                             T crit = R2t;
                             if (MODE == 2) {
-                                const T Hj = mul_unfused(a.eps, hj);
+                                const T Hj = mul_unfused(a.eps, hj) * a.hmargin;
                                 crit = max(crit, mul_unfused(Hj, Hj));
                             }
                             pass = d2 < crit;
@@ -425,6 +427,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.cnt = b.cnt;
     a.eps = (T)sc.eps;
     a.margin = (T)margin;
+    a.hmargin = (T)1;
     a.leaf_max = sc.leaf_max;
     a.pos4 = (const V4<T>*)b.pos4;
     a.n = b.n;
@@ -436,8 +439,16 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
 template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s) {
     if (b.n <= 0) return;
-    const double margin = (mode == 0 && !(sc.flags & SWSPH_FIXED_H)) ? DENS_MARGIN : 1.0;
+    const bool guessed = (mode == 0 || mode == 3) && !(sc.flags & SWSPH_FIXED_H);
+    const double margin = guessed ? DENS_MARGIN : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
+    if (mode == 3) {
+        // the force loop's lists before h is known: every support at the
+        // density margin over its guess (supersets of the lists at the final
+        // h wherever no h ends beyond that margin)
+        a.hmargin = (T)margin;
+        mode = 2;
+    }
     // the density builds stop refining at 8x larger cells: their search (a
     // chain of dependent cell-table loads, most of the build's time) gets
     // shallower and the walk over the leaves' particles, which culls each
@@ -445,7 +456,7 @@ void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipS
     // whose cells also pass on their largest support, keeps leaf_max
     if (mode == 0) a.leaf_max = std::min(sc.leaf_max * 8, 4096);
     if (fixup) {
-        // the flagged density tiles, compacted by k_fix_list
+        // the flagged tiles (b.tflag), compacted into b.tmpidx
         a.list = b.tmpidx;
         a.ntiles = &b.cnt->n_fix;
     }

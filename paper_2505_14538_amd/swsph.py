@@ -31,6 +31,7 @@ NO_VISC = 0x2
 PER_TASK_LAUNCH = 0x4
 FLAT_LAUNCH = 0x8
 TIMING = 0x10
+SINGLE_LAUNCH = 0x20
 
 ST_CAPACITY, ST_REACH, ST_NEWTON, ST_DOMAIN = 0x1, 0x2, 0x4, 0x8
 
@@ -108,7 +109,8 @@ class Stats(ctypes.Structure):
                 ("newton_sweeps", ctypes.c_uint64), ("newton_max", ctypes.c_uint32),
                 ("newton_failed", ctypes.c_uint32), ("listed", ctypes.c_uint64),
                 ("restages", ctypes.c_uint64), ("n_tiles_dens", ctypes.c_uint64),
-                ("dens_listed", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 4)]
+                ("dens_listed", ctypes.c_uint64), ("single_redo", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 3)]
 
     def as_dict(self) -> Dict:
         return {"status": self.status, "n_tiles": self.n_tiles,
@@ -116,7 +118,7 @@ class Stats(ctypes.Structure):
                 "newton_sweeps": self.newton_sweeps, "newton_max": self.newton_max,
                 "newton_failed": self.newton_failed, "listed": self.listed,
                 "restages": self.restages, "n_tiles_dens": self.n_tiles_dens,
-                "dens_listed": self.dens_listed}
+                "dens_listed": self.dens_listed, "single_redo": self.single_redo}
 
 
 _vp = ctypes.c_void_p
