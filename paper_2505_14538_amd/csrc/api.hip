@@ -156,7 +156,8 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.trad_d = take(4 * (uint64_t)toff);
     l.fredo = take(4 * (uint64_t)toff);
     l.forder = take(4 * 2 * (uint64_t)toff);
-    l.boxph = take(4 * (32 + 2) * (uint64_t)n_box);  // phase words a cache line apart
+    // phase words a cache line apart, totals, radii, and the all-boxes word
+    l.boxph = take(4 * ((32 + 2) * (uint64_t)n_box + 64));
     l.d_out = take(10 * T * N);
     l.d_int = take(2 * 4 * N);
     l.g_out = take(3 * T * N);

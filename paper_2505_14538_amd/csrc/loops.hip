@@ -1035,15 +1035,35 @@ __global__ void k_single_order(const int32_t* __restrict__ order_d,
 }
 
 // ready: the box this wavefront last found complete (no second wait or
-// acquire for its further tiles).
+// acquire for its further tiles), or READY_ALL once every density tile of
+// every box is done and acquired (one acquire for the rest of the launch).
+constexpr int READY_ALL = -2;
+
+// Word counting every box's density tiles done (its own cache line).
+__device__ __forceinline__ int64_t box_all_word(int32_t n_box) {
+    return ((int64_t)(BOX_STRIDE + 2) * n_box + BOX_STRIDE - 1) / BOX_STRIDE * BOX_STRIDE;
+}
+
 template <typename T, int CAP>
 __device__ __forceinline__ void single_force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>& a, int t,
-                                                  WaveStats& ws, int& ready) {
+                                                  WaveStats& ws, int& ready, int64_t nd) {
     const Tile tl = a.tiles[t];
     const int count = uniform(tl.count), box = uniform(tl.box);
     if (count <= 0) return;
     const int lane = lane_id();
-    if (box != ready) {
+    if (ready != READY_ALL) {
+        int all = 0;
+        if (lane == 0)
+            all = (int64_t)__hip_atomic_load(&a.boxph[box_all_word(a.n_box)], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT) >= nd;
+        if (__shfl(all, 0, WAVE)) {
+            __threadfence();  // acquire every box's density results at once
+            ready = READY_ALL;
+        }
+    }
+    if (ready == READY_ALL) {
+        if (a.boxph[box * BOX_STRIDE] & BOX_REDO) return;
+    } else if (box != ready) {
     uint32_t w = BOX_REDO;
     if (lane == 0) {
         const uint32_t need = a.boxph[BOX_STRIDE * a.n_box + box];
@@ -1112,6 +1132,7 @@ k_single(KArgs<T> ad, KArgs<T> af, KArgs<T> aq) {
         if (lane_id() == 0) {
             if (sredo) atomicOr(&ad.boxph[sbox * BOX_STRIDE], BOX_REDO);
             atomicAdd(&ad.boxph[sbox * BOX_STRIDE], scnt);
+            atomicAdd(&ad.boxph[box_all_word(ad.n_box)], scnt);
         }
         sbox = -1;
         scnt = 0;
@@ -1140,7 +1161,8 @@ k_single(KArgs<T> ad, KArgs<T> af, KArgs<T> aq) {
             ++scnt;
         } else {
             release();
-            single_force_tile<T, CAPF>(*(WaveMem<T, CAPF, 4>*)wm, af, (int)(k - nd), wsf, ready);
+            single_force_tile<T, CAPF>(*(WaveMem<T, CAPF, 4>*)wm, af, (int)(k - nd), wsf, ready,
+                                       nd);
         }
     });
     release();
@@ -1238,6 +1260,8 @@ int launch_single(const BinPtrs& bin, const Scheme& sc, int lds_cap_d, int lds_c
     uint32_t* total = bin.boxph + (int64_t)BOX_STRIDE * nb;
     uint32_t* rmin = total + nb;
     launch_fill_u32(bin.boxph, (int64_t)BOX_STRIDE * nb, 0u, s);
+    const int64_t all_word = ((int64_t)(BOX_STRIDE + 2) * nb + BOX_STRIDE - 1) / BOX_STRIDE * BOX_STRIDE;
+    launch_fill_u32(bin.boxph + all_word, 1, 0u, s);
     launch_fill_u32(rmin, nb, 0x7f7fffffu, s);  // FLT_MAX
     launch_fill_u32(bin.fredo, bin.tile_cap, 0u, s);
     hipLaunchKernelGGL(k_box_tiles, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
