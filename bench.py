@@ -18,7 +18,8 @@ tile task (the per-task offload baseline), a warm-started step (the previous
 h as the guess), the autotuner's choice, the roofline entry of the dominant
 kernel (with FP32 VALU counter figures and HBM traffic from the committed
 rocprofv3 summaries while the kernel sources match them), the many-boxes set
-(256 boxes in one launch per loop), the differentiation set (forward and
+(256 boxes in one launch per loop, and all three loops of every box in one
+launch), the differentiation set (forward and
 adjoint), the Gresho-Chan vortex integrated with the switch loops, and the
 FP64 oracle on the host cores.
 """
@@ -175,7 +176,8 @@ def pairs_of(d, f):
 def many_boxes_leg(S, W, args):
     """The many-boxes set (256 independent periodic boxes, ~4.7M particles):
     one graph-replayed step of all boxes, every loop one persistent launch
-    over the tiles of all boxes."""
+    over the tiles of all boxes; then the single-launch step (the density,
+    gradient and force loops of every box in one launch)."""
     log("many-boxes workload")
     parts = W.many_boxes()
     dp = S.to_device(parts)
@@ -188,12 +190,24 @@ def many_boxes_leg(S, W, args):
     sweeps = st["newton_sweeps"] / max(1, st["n_tiles_dens"])
     fl = step_flops(P_d, P_f, sweeps)
     log("many boxes: %.3f ms per step" % ms)
+    # the same step with all three loops of every box in one launch
+    single = S.Plan(flags=S.SINGLE_LAUNCH)
+    ms1, (d1, g1, f1) = timed_steps(single, dp, args.steps, args.warmup)
+    st1 = single.stats()
+    if st1["code"] != 0:
+        raise SystemExit("many boxes, single launch: device status %s" % st1)
+    Q_d, Q_f = pairs_of(d1, f1)
+    log("many boxes, single launch: %.3f ms per step (%d of %d gradient/force tiles redone)"
+        % (ms1, st1["single_redo"], st1["n_tiles"]))
     return {"workload": "256 periodic unit boxes, N_b log-uniform in [2048, 65536] rounded to "
                         "cubes, jittered lattices, FP32", "n": parts.n, "n_box": parts.n_box,
             "ms_per_step": ms, "value": (P_d + P_f) / (ms * 1e-3),
             "unit": "pair interactions/s",
             "frac_fp32_peak": sum(fl.values()) / (ms * 1e-3) / PEAK_FP32,
-            "newton_sweeps_per_tile": sweeps}
+            "newton_sweeps_per_tile": sweeps,
+            "single_launch": {"ms_per_step": ms1, "value": (Q_d + Q_f) / (ms1 * 1e-3),
+                              "redone_tiles": st1["single_redo"], "tiles": st1["n_tiles"],
+                              "vs_separate_launches": ms / ms1}}
 
 
 def diff_leg(S, W, args):
