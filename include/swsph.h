@@ -238,8 +238,8 @@ int swsph_density(swsph_plan* plan, const swsph_particles* p, swsph_density_out*
 /* Gradient loop (Sec. 2.1.3) at the density results d.  The gradient and
  * force loops run in one kernel (one task build, one staging, one pass of
  * distance tests): this call and swsph_force each run it and copy out their
- * own outputs, and swsph_step runs it once for both; all three give the
- * same bits. */
+ * own outputs; swsph_gradient_force and swsph_step run it once for both;
+ * all give the same bits. */
 int swsph_gradient(swsph_plan* plan, const swsph_particles* p,
                    const swsph_density_out* d, swsph_gradient_out* o, void* ws,
                    void* stream);
@@ -248,6 +248,14 @@ int swsph_gradient(swsph_plan* plan, const swsph_particles* p,
  * the density results d. */
 int swsph_force(swsph_plan* plan, const swsph_particles* p, const swsph_density_out* d,
                 swsph_force_out* o, void* ws, void* stream);
+
+/* The gradient (Sec. 2.1.3) and force (Sec. 2.1.4) loops together, at the
+ * density results d: one task build and one pass of the joint kernel write
+ * both outputs (the same bits as swsph_gradient and swsph_force, at the cost
+ * of one of them).  go and fo are both required (SWSPH_E_ARG otherwise). */
+int swsph_gradient_force(swsph_plan* plan, const swsph_particles* p,
+                         const swsph_density_out* d, swsph_gradient_out* go,
+                         swsph_force_out* fo, void* ws, void* stream);
 
 /* Adjoint of density -> force: given dL/da and dL/d(du/dt), overwrite gi
  * with dL/dx, dL/dv, dL/du, dL/dm, differentiating through rho, f and h

@@ -656,6 +656,12 @@ int swsph_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_ou
     return gf_checked(pl, p, d, nullptr, o, ws, stream);
 }
 
+int swsph_gradient_force(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
+                         swsph_gradient_out* go, swsph_force_out* fo, void* ws, void* stream) {
+    if (pl && (!go || !fo)) return fail(SWSPH_E_ARG, "gradient and force outputs are required");
+    return gf_checked(pl, p, d, go, fo, ws, stream);
+}
+
 int swsph_gradient_force_sw(swsph_plan* pl, const swsph_particles* p, const swsph_density_out* d,
                             const swsph_switch_params* sp, swsph_switch_state* st,
                             swsph_gradient_out* go, swsph_force_out* fo, void* ws,

@@ -135,6 +135,8 @@ _lib.swsph_bin.argtypes = [_vp, _P(ParticlesC), _vp, _vp]
 _lib.swsph_density.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _vp, _vp]
 _lib.swsph_gradient.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut), _vp, _vp]
 _lib.swsph_force.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(ForceOut), _vp, _vp]
+_lib.swsph_gradient_force.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut),
+                                      _P(ForceOut), _vp, _vp]
 _lib.swsph_force_backward.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(ForceGrad),
                                       _P(InputGrad), _vp, _vp]
 _lib.swsph_step.argtypes = [_vp, _P(ParticlesC), _P(DensityOut), _P(GradientOut), _P(ForceOut),
@@ -154,7 +156,8 @@ _lib.swsph_reset_timers.argtypes = [_vp]
 
 EXPORTS = ["swsph_version", "swsph_last_error", "swsph_config_default", "swsph_plan_create",
            "swsph_plan_destroy", "swsph_workspace_bytes", "swsph_bin", "swsph_density",
-           "swsph_gradient", "swsph_force", "swsph_force_backward", "swsph_step",
+           "swsph_gradient", "swsph_force", "swsph_gradient_force", "swsph_force_backward",
+           "swsph_step",
            "swsph_step_static", "swsph_gradient_force_sw", "swsph_kick_drift",
            "swsph_read_stats", "swsph_autotune", "swsph_plan_get_tuning",
            "swsph_kernel_times", "swsph_reset_timers"]
@@ -347,6 +350,23 @@ class Plan:
         _check(_lib.swsph_force(self.h, ctypes.byref(pc), ctypes.byref(dc), ctypes.byref(fo),
                                 self._ws_ptr(), _stream()))
         return o
+
+    def gradient_force(self, p: DeviceParticles, dens):
+        """Gradient and force outputs from one pass of the joint kernel
+        (swsph_gradient_force); returns (gradient outputs, force outputs)."""
+        torch = _torch()
+        n = p.n
+        g = {"v_sig": self._alloc(n), "lap_u": self._alloc(n)}
+        f = {k: self._alloc(n) for k in ("ax", "ay", "az", "dudt")}
+        f["nint"] = self._alloc(n, torch.int32)
+        go = GradientOut(_ptr(g["v_sig"]), _ptr(g["lap_u"]))
+        fo = ForceOut(**{k: _ptr(v) for k, v in f.items()})
+        pc = p.c()
+        dc = self._dens_c(dens)
+        _check(_lib.swsph_gradient_force(self.h, ctypes.byref(pc), ctypes.byref(dc),
+                                         ctypes.byref(go), ctypes.byref(fo), self._ws_ptr(),
+                                         _stream()))
+        return g, f
 
     def gradient_force_sw(self, p: DeviceParticles, dens, dt: float, state, **params):
         """Gradient and force loops with the time-dependent switches

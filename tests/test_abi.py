@@ -94,6 +94,8 @@ def test_calls_reject_bad_particles_on_host(S):
     fo = S.ForceOut()
     assert S._lib.swsph_force(p.h, ctypes.byref(pc), ctypes.byref(d), ctypes.byref(fo), ws,
                               None) == -1                                  # u missing
+    assert S._lib.swsph_gradient_force(p.h, ctypes.byref(pc), ctypes.byref(d), None,
+                                       ctypes.byref(fo), ws, None) == -1   # gradient output
     st = S.Stats()
     assert S._lib.swsph_read_stats(p.h, ws, ctypes.byref(st), None) == -3
     # FIXED_H needs h

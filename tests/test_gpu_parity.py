@@ -207,6 +207,25 @@ def test_step_graph_replays_match_separate_calls(S):
     assert plan.stats()["code"] == 0
 
 
+def test_joint_gradient_force_call_equals_separate_calls(S):
+    """swsph_gradient_force (one task build, one joint kernel pass) writes
+    the same bits as swsph_gradient and swsph_force called one by one."""
+    import torch
+    p = W.sedov(nside=20)
+    plan = S.Plan()
+    dp = S.to_device(p)
+    plan.bin(dp)
+    d = plan.density(dp)
+    g1 = plan.gradient(dp, d)
+    f1 = plan.force(dp, d)
+    g2, f2 = plan.gradient_force(dp, d)
+    torch.cuda.synchronize()
+    for a, b in ((S.host(g1), S.host(g2)), (S.host(f1), S.host(f2))):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    assert plan.stats()["code"] == 0
+
+
 def test_autotune_keeps_results(S, oracle_mod, tmp_path):
     O = oracle_mod
     p = W.tiny(nside=12)
