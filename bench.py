@@ -86,7 +86,7 @@ def cpu_baseline(parts):
     t_d = time.time() - t0
     P_d = float(np.sum(d["nngb"]))
     rng = np.random.default_rng(5)
-    ns = 200000
+    ns = 1000000
     idx = np.sort(rng.choice(parts.n, ns, replace=False))
     t0 = time.time()
     f = O.force(parts, d, prm, idx=idx)
