@@ -260,7 +260,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
             tested += (unsigned long long)ns;  // per i-particle
             wave_sync();
         }
-        constexpr int U = 4;   // list entries of a stream in flight together
+        constexpr int U = 2;   // list entries of a stream in flight together
         constexpr int UF = 2;  // the same in the full sweep (two global loads each)
         if (listed) {
             // stream js of slot li takes entries js, js + S, ... of li's list
