@@ -255,9 +255,40 @@ void launch_scatter_stable(int64_t n, const uint32_t* keys, const int32_t* slot,
 // ---------------------------------------------------------------- gather
 
 // Sorted copies: pos4 = (x, y, z, m), vel4 = (vx, vy, vz, u), hs = h guess.
-// Without a guess, h0 = eta * w_l / cbrt(N_l) from the first enclosing cell
-// (walking up from the fine cell) that holds at least 16 particles, blended
-// with the child cell's estimate where that cell holds more than 32.
+// Without a guess, h0 is the geometric mean of two estimates eta / cbrt(n)
+// of the local number density n: (1) n = N_l / w_l^3 of the first enclosing
+// cell (walking up from the fine cell) that holds at least 16 particles,
+// blended with the child cell's estimate where that cell holds more than
+// 32; (2) n = N / (3 w)^3 of the first block of 3 x 3 x 3 cells centred on
+// the particle's cell (periodic) that holds at least 16.  A particle near a
+// cell's face gets its density from its own cell only in (1) and from a
+// neighbourhood about itself in (2); on the clustered 128^3 set (a host
+// simulation against the solved h) the mean gives density tiles whose root
+// lies beyond their staged radius 4x less often (3.1 % -> 0.8 %) for 1.4 %
+// more staged volume.
+__device__ inline double block_estimate(const BoxInfo& bi, uint32_t mort, int k,
+                                        const int32_t* __restrict__ cstart, double eta) {
+    const uint32_t cx = compact3(mort), cy = compact3(mort >> 1), cz = compact3(mort >> 2);
+    for (int lev = k; lev >= 0; --lev) {
+        const int sh = k - lev;
+        const uint32_t q = 1u << lev;
+        const uint32_t bx = cx >> sh, by = cy >> sh, bz = cz >> sh;
+        int64_t tot = 0;
+        for (int d = 0; d < 27; ++d) {
+            const uint32_t ox = (bx + q + (uint32_t)(d % 3) - 1u) & (q - 1u);
+            const uint32_t oy = (by + q + (uint32_t)((d / 3) % 3) - 1u) & (q - 1u);
+            const uint32_t oz = (bz + q + (uint32_t)(d / 9) - 1u) & (q - 1u);
+            const int64_t fb = bi.fine_off + ((int64_t)morton3(ox, oy, oz) << (3 * sh));
+            tot += cstart[fb + ((int64_t)1 << (3 * sh))] - cstart[fb];
+        }
+        if (tot >= 16 || lev == 0) {
+            const double w = bi.L / (double)q;
+            return eta * 3.0 * w / cbrt((double)(tot > 0 ? tot : 1));
+        }
+    }
+    return 0.0;
+}
+
 template <typename T>
 __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
                          const T* __restrict__ z, const T* __restrict__ vx,
@@ -305,6 +336,8 @@ __global__ void k_gather(int64_t n, const T* __restrict__ x, const T* __restrict
             const double hc = eta * 0.5 * w / cbrt((double)(child > 0 ? child : 1));
             hg = sqrt(hg * hc);
         }
+        const double hb = block_estimate(bi, mort, k, cstart, eta);
+        if (hb > 0.0) hg = sqrt(hg * hb);
         h = (T)hg;
     }
     hs[s] = h;
