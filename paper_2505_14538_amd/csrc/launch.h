@@ -8,7 +8,10 @@ namespace swsph {
 
 // Density task lists reach this factor beyond the largest guessed support of
 // their tile (the Newton iteration's room before a fix-up pass).
-constexpr double DENS_MARGIN = 1.25;
+constexpr double DENS_MARGIN = 1.2;
+// The same factor for the single-launch step, whose boxes are redone whole
+// when any of their roots lies beyond it (a wider margin pays there).
+constexpr double SINGLE_MARGIN = 1.25;
 
 // Events around loop-kernel launches (SWSPH_TIMING); owned by the plan.
 struct Timer;

@@ -1280,6 +1280,7 @@ int launch_single(const BinPtrs& bin, const Scheme& sc, int lds_cap_d, int lds_c
     ad.trad = bin.trad_d;  // fix-up radii: the lists' radii stay for the check above
     ad.dens4_out = (V4<T>*)bin.dens4;
     ad.hguess = hguess;
+    if (!(sc.flags & SWSPH_FIXED_H)) ad.dmargin = (T)SINGLE_MARGIN;
     ad.boxph = bin.boxph;
     KArgs<T> af = make_args<T>(bin, sc);
     af.out = (T*)bin.f_out;

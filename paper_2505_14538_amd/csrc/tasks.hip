@@ -440,7 +440,7 @@ template <typename T>
 void launch_tasks(const BinPtrs& b, const Scheme& sc, int mode, bool fixup, hipStream_t s) {
     if (b.n <= 0) return;
     const bool guessed = (mode == 0 || mode == 3) && !(sc.flags & SWSPH_FIXED_H);
-    const double margin = guessed ? DENS_MARGIN : 1.0;
+    const double margin = guessed ? (mode == 3 ? SINGLE_MARGIN : DENS_MARGIN) : 1.0;
     TArgs<T> a = targs<T>(b, sc, margin);
     if (mode == 3) {
         // the force loop's lists before h is known: every support at the
