@@ -160,7 +160,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
     };
     auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
-        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+        return ok & (dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2);
     };
     auto sweep = [&](int ns) {
         pair_loop(m, ns, js, S, test, body_k);
@@ -527,9 +527,11 @@ __device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>
     auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        const bool in = ok && act && r2 < max(H2, sj.w);
+        // no short-circuit: the whole 4-vector is read up front, so the
+        // reads of consecutive tests issue together
+        const bool in = ok & act & ((r2 < H2) | (r2 < sj.w));
         hits += in ? 1 : 0;
-        return in && r2 > (T)0;
+        return in & (r2 > (T)0);
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];
@@ -551,7 +553,7 @@ __device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>
         const T mu = vdote < (T)0 ? vdote : (T)0;
         const T vs = ci + vj.w - beta * mu;
         T nu = 0;
-        if (visc) nu = -alpha * mu * vs / (rhoi + rhoj);
+        if (visc) nu = -alpha * mu * vs * fast_rcp(rhoi + rhoj);
         // gradient loop: signal speed and the Laplacian of u
         const T q = r * invH;
         const T t1 = (T)1 - q;
@@ -639,7 +641,7 @@ __device__ void grad_sw_tile(WaveMem<T, CAP, 3>& m, const KArgs<T>& a, int t, Wa
     unsigned long long tested = 0;
     auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
-        return ok && dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2;
+        return ok & (dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z) < H2);
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];   // (x, y, z, m_j / rho_j)
@@ -721,9 +723,11 @@ __device__ void force_sw_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t, W
     auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        const bool in = ok && act && r2 < max(H2, sj.w);
+        // no short-circuit: the whole 4-vector is read up front, so the
+        // reads of consecutive tests issue together
+        const bool in = ok & act & ((r2 < H2) | (r2 < sj.w));
         hits += in ? 1 : 0;
-        return in && r2 > (T)0;
+        return in & (r2 > (T)0);
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];
@@ -743,11 +747,11 @@ __device__ void force_sw_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t, W
         const T vdote = vr * inv_r;
         const T mu = vdote < (T)0 ? vdote : (T)0;
         const T vs = ci + vj.w - a.beta * mu;
-        const T rsum = rhoi + rhoj;
+        const T irs = fast_rcp(rhoi + rhoj);
         T nu = 0;
         if (visc) {
             const T aij = (T)0.25 * (swi.x + wj.x) * (swi.y + wj.y);
-            nu = -aij * mu * vs / rsum;
+            nu = -aij * mu * vs * irs;
         }
         const T mfg = cj.x * fi * gi + cj.z * gj;
         const T sa = cj.x * Ai * gi + cj.y * gj + (T)0.5 * nu * mfg;
@@ -759,9 +763,9 @@ __device__ void force_sw_tile(WaveMem<T, CAP, 5>& m, const KArgs<T>& a, int t, W
         // artificial conduction
         const T Pj = ej.y;
         const T psum = Pi + Pj;
-        const T acij = psum > (T)0 ? (Pi * swi.z + Pj * wj.z) / psum : (T)0;
-        const T vc = fabs(vdote) + sqrt((T)2 * fabs(Pi - Pj) / rsum);
-        du += acij * vc * (ui - ej.z) * mfg / rsum;
+        const T acij = psum > (T)0 ? (Pi * swi.z + Pj * wj.z) * fast_rcp(psum) : (T)0;
+        const T vc = fabs(vdote) + sqrt((T)2 * fabs(Pi - Pj) * irs);
+        du += acij * vc * (ui - ej.z) * mfg * irs;
     };
     auto sweep = [&](int ns) {
         pair_loop(m, ns, js, S, test, body);

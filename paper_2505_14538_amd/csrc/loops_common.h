@@ -161,12 +161,14 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
             const int k = k0 + js + u * S;
             hit[u] = test(k < ns ? k : ns - 1, k < ns);
         }
+        // appended without a branch: every index is written at slot c and
+        // kept by advancing c on a hit.  A list holds at most HL - PL_U
+        // entries when a group starts (drained otherwise), so every write
+        // stays below HL; a slot at or past c is never read.
 #pragma unroll
         for (int u = 0; u < PL_U; ++u) {
-            if (hit[u]) {
-                m.lst[c][lane] = (uint16_t)(k0 + js + u * S);
-                ++c;
-            }
+            m.lst[c][lane] = (uint16_t)(k0 + js + u * S);
+            c += hit[u] ? 1 : 0;
         }
         if (ballot(c > WM::HL - PL_U) != 0ull) drain();
     }
