@@ -540,14 +540,14 @@ __device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>
         const T H2j = sj.w;
         const V4<T> vj = m.s[1][k];
         const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
-        const V4<T> ej = m.s[3][k];  // (rho_j, j, u_j, m_j / rho_j)
+        const V4<T> ej = m.s[3][k];  // (rho_j, 8/(pi H_j^4), u_j, m_j / rho_j)
         const T rhoj = ej.x;
         const T inv_r = fast_rsqrt(r2);
         const T r = r2 * inv_r;
         const bool gin = r2 < H2;  // inside the support of i: a gradient pair
         const T gi = gin ? kgi * m4_dw(r * invH) : (T)0;
         const T ihj = cj.w;
-        const T gj = r2 < H2j ? cn * ihj * ihj * ihj * ihj * m4_dw(r * ihj) : (T)0;
+        const T gj = r2 < H2j ? ej.y * m4_dw(r * ihj) : (T)0;
         const T vr = (vi.x - vj.x) * dx + (vi.y - vj.y) * dy + (vi.z - vj.z) * dz;
         const T vdote = vr * inv_r;
         const T mu = vdote < (T)0 ? vdote : (T)0;

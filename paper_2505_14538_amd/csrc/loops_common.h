@@ -131,10 +131,10 @@ template <typename V> __device__ __forceinline__ V stream_max(V v, const LaneMap
 // thus runs with nearly all lanes busy instead of under the divergence of
 // the test (only a few of the tested pairs lie inside the support), and
 // each lane still accumulates its pairs in staged order, so results do not
-// depend on the list length.  Tests go PL_U at a time (their LDS reads issue together),
-// the body two at a time (the second pair's reads overlap the first's
-// arithmetic); loop control is wavefront-uniform.  test(k, ok) must return
-// false when !ok (k is then a valid but repeated index).
+// depend on the list length.  Tests go PL_U at a time, the body two at a
+// time (the second pair's reads overlap the first's arithmetic); loop
+// control is wavefront-uniform.  test(k, ok) must return false when !ok (k
+// is then a valid but repeated index).
 constexpr int PL_U = 4;
 
 template <class WM, class Test, class Body>
@@ -367,12 +367,17 @@ __device__ int stage_tile(WM& m, const KArgs<T>& a, int lt, const BoxInfo& bi, c
                 // are read from global memory for the pairs inside)
                 q0 = V4<T>{xs, ys, zs, int_as<T>(j)};
             } else if (LK == L_FORCE) {
+                // per candidate, not per pair: 1/H_j and the kernel
+                // gradient's normalisation 8/(pi H_j^4), reciprocals (the
+                // hardware's in FP32) instead of divisions
                 const V4<T> da = r.d;
                 const T Hj = mul_unfused(a.eps, r.h);
+                const T ihj = fast_rcp(Hj);
+                const T ih2 = ihj * ihj;
                 q0 = V4<T>{xs, ys, zs, mul_unfused(Hj, Hj)};
                 q1 = V4<T>{va.x, va.y, va.z, da.z};
-                q2 = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, (T)1 / Hj};
-                q3 = V4<T>{da.x, int_as<T>(j), va.w, pa.w / da.x};
+                q2 = V4<T>{pa.w, pa.w * da.w, pa.w * da.y, ihj};
+                q3 = V4<T>{da.x, (T)(8.0 / PI_D) * ih2 * ih2, va.w, pa.w * fast_rcp(da.x)};
             } else if (LK == L_GSW) {
                 // gradient loop with switches: (m_j / rho_j), c_j, u_j and
                 // alpha_V,j (aux4 = alpha_V, B, alpha_c, 0)
