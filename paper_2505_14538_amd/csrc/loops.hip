@@ -520,18 +520,16 @@ __device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>
     T vsig = (T)2 * ci, lap = 0;  // gradient loop
     int ginside = 0;
     unsigned long long tested = 0;
-    // hits: every j (self included) with r < max(H_i, H_j); the self pair and
-    // coincident pairs (r = 0) add nothing to a and du/dt, so only r > 0 goes
-    // to the body, and nint = hits - 1 (the self pair is staged exactly once)
+    // hits: every j (self included) with r < max(H_i, H_j), counted in the
+    // body (nint = hits - 1: the self pair is staged exactly once).  The self
+    // pair and coincident pairs (r = 0) add nothing: 1/r is taken as 0 there,
+    // which zeroes their a and du/dt terms, and the gradient terms skip them.
     int hits = 0;
     auto test = [&](int k, bool ok) {
         const V4<T> sj = m.s[0][k];
         const T r2 = dist2_unfused(pi.x - sj.x, pi.y - sj.y, pi.z - sj.z);
-        // no short-circuit: the whole 4-vector is read up front, so the
-        // reads of consecutive tests issue together
-        const bool in = ok & act & ((r2 < H2) | (r2 < sj.w));
-        hits += in ? 1 : 0;
-        return in & (r2 > (T)0);
+        // no short-circuit: the whole 4-vector is read up front
+        return ok & act & (r2 < max_sq(H2, sj.w));
     };
     auto body = [&](int k) {
         const V4<T> sj = m.s[0][k];
@@ -542,9 +540,11 @@ __device__ __forceinline__ void force_tile(WaveMem<T, CAP, 4>& m, const KArgs<T>
         const V4<T> cj = m.s[2][k];  // (m_j, m_j A_j, m_j f_j, 1/H_j)
         const V4<T> ej = m.s[3][k];  // (rho_j, 8/(pi H_j^4), u_j, m_j / rho_j)
         const T rhoj = ej.x;
-        const T inv_r = fast_rsqrt(r2);
+        ++hits;
+        const bool pos = r2 > (T)0;
+        const T inv_r = pos ? fast_rsqrt(r2) : (T)0;
         const T r = r2 * inv_r;
-        const bool gin = r2 < H2;  // inside the support of i: a gradient pair
+        const bool gin = pos & (r2 < H2);  // inside the support of i: a gradient pair
         const T gi = gin ? kgi * m4_dw(r * invH) : (T)0;
         const T ihj = cj.w;
         const T gj = r2 < H2j ? ej.y * m4_dw(r * ihj) : (T)0;

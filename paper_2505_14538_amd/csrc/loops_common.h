@@ -3,6 +3,8 @@
 // j-particles from its task list, and M4 kernel pieces.
 #pragma once
 
+#include <type_traits>
+
 #include "launch.h"
 #include "search.h"
 
@@ -154,12 +156,15 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
         c = 0;
     };
     const int step = S * PL_U;
-    for (int k0 = 0; k0 < ns; k0 += step) {
+    // one group of PL_U tests per lane; a full group (k0 + step <= ns) needs
+    // no bounds checks, only the last one does
+    auto group = [&](int k0, auto full) {
         bool hit[PL_U];
 #pragma unroll
         for (int u = 0; u < PL_U; ++u) {
             const int k = k0 + js + u * S;
-            hit[u] = test(k < ns ? k : ns - 1, k < ns);
+            if constexpr (decltype(full)::value) hit[u] = test(k, true);
+            else hit[u] = test(k < ns ? k : ns - 1, k < ns);
         }
         // appended without a branch: every index is written at slot c and
         // kept by advancing c on a hit.  A list holds at most HL - PL_U
@@ -171,7 +176,10 @@ __device__ __forceinline__ void pair_loop(WM& m, int ns, int js, int S, Test&& t
             c += hit[u] ? 1 : 0;
         }
         if (ballot(c > WM::HL - PL_U) != 0ull) drain();
-    }
+    };
+    int k0 = 0;
+    for (; k0 + step <= ns; k0 += step) group(k0, std::true_type{});
+    if (k0 < ns) group(k0, std::false_type{});
     drain();
 }
 
@@ -467,6 +475,15 @@ template <typename T> __device__ __forceinline__ T m4_q2w2(T q) {
     return q < (T)0.5 ? a : b;
 }
 // w'(q)
+// The larger of two squared radii (b >= 0, a >= 0 or a = -1 for an unused
+// lane; neither NaN).  FP32: as integers, since the bit patterns of
+// non-negative floats order as the floats do and a negative a loses to any b
+// (no NaN quieting, which the float max needs).
+__device__ __forceinline__ float max_sq(float a, float b) {
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
+__device__ __forceinline__ double max_sq(double a, double b) { return a > b ? a : b; }
+
 template <typename T> __device__ __forceinline__ T m4_dw(T q) {
     const T t = (T)1 - q;
     const T a = q * ((T)18 * q - (T)12), b = (T)-6 * t * t;
