@@ -117,7 +117,7 @@ typedef struct swsph_config {
     int32_t h_max_iter;  /* Newton sweeps before SWSPH_ST_NEWTON is latched */
     int32_t dtype;       /* swsph_dtype of every particle array */
     uint32_t flags;      /* SWSPH_* flags above */
-    int32_t tile;        /* most i-particles per gradient/force task: 8, 16, 32, 64 (0: 32) */
+    int32_t tile;        /* most i-particles per gradient/force task: 8, 16, 32, 64 (0: 64) */
     int32_t lds_cap;     /* staged j-particles per wavefront: 128, 256, 512 (0: 128) */
     int32_t order;       /* task order: 0 cost-descending, 1 Morton cut into one
                             segment per XCD (default) */

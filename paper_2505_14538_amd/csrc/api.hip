@@ -410,7 +410,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     swsph_plan* pl = new (std::nothrow) swsph_plan();
     if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
     pl->cfg = *cfg;
-    pl->tile = cfg->tile ? cfg->tile : 32;
+    pl->tile = cfg->tile ? cfg->tile : 64;
     pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 8;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
     pl->lds_cap_d = cfg->lds_cap_dens ? cfg->lds_cap_dens : 512;
