@@ -66,14 +66,31 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
     if (tl.count <= 0) return 0;
     if (a.fixup && a.tflag[t] == 0) return 0;
     const int lane = lane_id();
-    const GroupMap q = group_map(tl.count);
+    // A fix-up pass iterates only the particles an earlier pass left pending
+    // (it stores their next guess negated); the others keep their results,
+    // and the pending ones get all of the wavefront's streams.  A flagged
+    // tile with none marked runs whole.
+    int nsel = tl.count;
+    unsigned long long selm = 0ull;
+    if (a.fixup) {
+        selm = ballot(lane < tl.count && a.hs[tl.begin + lane] < (T)0);
+        if (selm) nsel = __popcll(selm);
+    }
+    const GroupMap q = group_map(nsel);
     const int js = q.js, S = q.S, c = q.c;
     const bool act = q.act;
     const bool lead = act && js == 0;  // writes the results of its i-particle
-    const int i = tl.begin + q.li;
+    int pos = q.li;  // the i-slot's particle within the tile
+    if (selm) {
+        unsigned long long mm = selm;
+        for (int r = 0; r < q.li; ++r) mm &= mm - 1ull;
+        pos = mm ? (int)__builtin_ctzll(mm) : 0;
+    }
+    const int i = tl.begin + pos;
     const BoxInfo bi = a.boxtab[tl.box];
     const V4<T> pi = a.pos4[i];
     T h = a.hs[i];
+    if (h < (T)0) h = -h;
     const bool fixed = (a.flags & SWSPH_FIXED_H) != 0;
     const TileGeom g = geom_of(tl);
     const T Rcap = (T)(0.5f * (float)bi.L * (1.0f - 1e-6f));
@@ -431,7 +448,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
             o[9 * n + i] = step_rcp((T)1 + h * drho * irho * ((T)1 / (T)3));
             a.iout[0 * n + i] = cnt - 1;
             a.iout[1 * n + i] = failed ? -iters : iters;
-            a.hs[i] = pend ? want : h;
+            a.hs[i] = pend ? -want : h;  // negated: pending, for the next pass
             if constexpr (SINGLE) {
                 const T gm1 = a.gamma - (T)1;
                 const T u = vi.w;
@@ -461,7 +478,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
             if (fmask) latch(a.cnt, R >= Rcap ? (SWSPH_ST_REACH | SWSPH_ST_NEWTON) : SWSPH_ST_NEWTON);
         }
         ws.restages += pmask ? 1ull : 0ull;
-        ws.tested += tested * (unsigned long long)tl.count;
+        ws.tested += tested * (unsigned long long)nsel;
         // per-lane statistics, reduced over the wavefront once per launch
         ws.lane_tested += tested_lane;
         ws.lane_inside += lead ? (unsigned long long)cnt : 0ull;
@@ -1152,11 +1169,12 @@ k_single(KArgs<T> ad, KArgs<T> af, KArgs<T> aq) {
             int code = density_tile<T, CAPD, true>(md, ad, k, wsd);
             if (code == 1) {
                 // an h needs a wider staged set: the tile's h (the converged
-                // ones, and the wider guesses the others asked for) are in
-                // hs; run it again at once when its gradient/force tile's
-                // list covers the wider radius (the fix-up path otherwise)
+                // ones, and, negated, the wider guesses the others asked
+                // for) are in hs; run it again at once when its
+                // gradient/force tile's list covers the wider radius (the
+                // fix-up path otherwise)
                 const int count = uniform(tl.count), begin = uniform(tl.begin);
-                const T hm = wave_max(lane_id() < count ? ad.hs[begin + lane_id()] : (T)0);
+                const T hm = wave_max(lane_id() < count ? fabs(ad.hs[begin + lane_id()]) : (T)0);
                 const float Rn = (float)(ad.eps * hm * (T)1.0625);
                 const float Rp = af.trad[uniform(ad.parent[k])];
                 if (Rn <= Rp) code = density_tile<T, CAPD, true>(md, ad, k, wsd, Rp);
