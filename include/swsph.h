@@ -123,7 +123,7 @@ typedef struct swsph_config {
                             segment per XCD (default) */
     int32_t leaf_max;    /* cell search: refine cells with more particles (0: 64;
                             the density task builds use 8x this, at most 4096) */
-    int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 8) */
+    int32_t tile_dens;   /* most i-particles per density task: 8, 16, 32, 64 (0: 16) */
     int32_t lds_cap_dens; /* staged j-particles per wavefront, density loop first pass
                              (0: 512; its fix-up passes stage up to 1024) */
     int32_t reserved[3];

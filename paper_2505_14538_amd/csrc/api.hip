@@ -42,7 +42,7 @@ struct Geometry {
     int64_t n = 0;
     int32_t n_box = 0;
     int32_t tile = 64;      // most particles per gradient/force tile
-    int32_t tile_d = 8;     // most particles per density tile
+    int32_t tile_d = 16;    // most particles per density tile
     int64_t tile_cap = 0;   // most tiles the bin can make (one per particle)
     int64_t n_fine = 0, n_pyr = 0;
     int64_t cand_cap = 0;
@@ -411,7 +411,7 @@ int swsph_plan_create(swsph_plan** out, const swsph_config* cfg) {
     if (!pl) return fail(SWSPH_E_ARG, "out of host memory");
     pl->cfg = *cfg;
     pl->tile = cfg->tile ? cfg->tile : 64;
-    pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 8;
+    pl->tile_d = cfg->tile_dens ? cfg->tile_dens : 16;
     pl->lds_cap = cfg->lds_cap ? cfg->lds_cap : 128;
     pl->lds_cap_d = cfg->lds_cap_dens ? cfg->lds_cap_dens : 512;
     pl->order = cfg->order;
