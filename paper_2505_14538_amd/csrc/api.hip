@@ -153,6 +153,7 @@ int build_geometry(Geometry& G, int64_t n, int32_t n_box, const int64_t* box_cou
     l.cands = take(4 * (uint64_t)G.cand_cap);
     l.trad = take(4 * (uint64_t)toff);
     l.tflag = take(4 * (uint64_t)toff);
+    l.fbox = take(4 * 6 * (uint64_t)toff);
     l.trad_d = take(4 * (uint64_t)toff);
     l.fredo = take(4 * (uint64_t)toff);
     l.forder = take(4 * 2 * (uint64_t)toff);
@@ -320,6 +321,7 @@ BinPtrs ptrs_of(const swsph_plan* pl, void* ws) {
     b.build_waves = pl->G.build_waves;
     b.trad = (float*)(w + l.trad);
     b.tflag = (int32_t*)(w + l.tflag);
+    b.fbox = (float*)(w + l.fbox);
     b.trad_d = (float*)(w + l.trad_d);
     b.fredo = (int32_t*)(w + l.fredo);
     b.forder = (int32_t*)(w + l.forder);

@@ -50,6 +50,8 @@ struct BinPtrs {
     int64_t build_waves;       // most task-build wavefronts (the capacity counts one window each)
     float* trad;
     int32_t* tflag;
+    float* fbox;               // density fix-ups: box of each flagged tile's pending
+                               // particles (lo xyz, hi xyz)
     float* trad_d;             // single-launch step: density fix-up radii
     int32_t* fredo;            // single-launch step: gradient/force tiles to redo
     int32_t* forder;           // single-launch step: the launch's task order

@@ -41,6 +41,7 @@ struct KArgs {
     int64_t cand_cap;
     float* trad;
     int32_t* tflag;
+    float* fbox;               // density fix-ups: box of each flagged tile's pending particles
     const V4<T>* pos4;
     const V4<T>* vel4;
     T* hs;
@@ -513,6 +514,7 @@ inline KArgs<T> make_args(const BinPtrs& b, const Scheme& sc) {
     a.cand_cap = b.cand_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
+    a.fbox = b.fbox;
     a.pos4 = (const V4<T>*)b.pos4;
     a.vel4 = (const V4<T>*)b.vel4;
     a.hs = (T*)b.hs;

@@ -81,7 +81,7 @@ struct Layout {
     uint64_t pos4, vel4, hs, dens4, hmaxpyr;
     uint64_t tiles, order, tiles_d, order_d, dparent, ord_table, ord_base;
     // task lists (candidate entries per tile) and density fix-up state
-    uint64_t cand_cnt, cand_off, cands, trad, tflag;
+    uint64_t cand_cnt, cand_off, cands, trad, tflag, fbox;
     // single-launch step: density fix-up radii, gradient/force tiles to
     // redo, the launch's task order, per-box phase words and tile totals
     uint64_t trad_d, fredo, forder, boxph;

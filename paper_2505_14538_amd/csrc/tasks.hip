@@ -30,6 +30,7 @@ struct TArgs {
     int64_t cand_cap;
     float* trad;
     const int32_t* tflag;
+    const float* fbox;  // density fix-ups: box of each flagged tile's pending particles
     Counters* cnt;
     T eps;
     T margin;   // on the tile's radius eps * hmax
@@ -165,6 +166,19 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
     TileGeom g;
 #pragma unroll
     for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
+    if (MODE == 0 && fixup && a.fbox) {
+        // a density fix-up iterates only the particles left pending (their
+        // h stored negated), inside the box the flagging pass recorded: the
+        // list serves that box (the loop culls with the same one)
+        const bool pend = lane < tl.count && a.hs[tl.begin + lane] < (T)0;
+        if (ballot(pend) != 0ull) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                g.lo[d] = a.fbox[6 * t + d];
+                g.hi[d] = a.fbox[6 * t + 3 + d];
+            }
+        }
+    }
     float Rstart = R;
     const float hm = (float)a.hmargin;
     if (MODE == 2) Rstart = fmaxf(R, a.hpyr[bi.pyr_off] * hm);
@@ -424,6 +438,7 @@ static TArgs<T> targs(const BinPtrs& b, const Scheme& sc, double margin) {
     a.cand_cap = b.cand_cap;
     a.trad = b.trad;
     a.tflag = b.tflag;
+    a.fbox = b.fbox;
     a.cnt = b.cnt;
     a.eps = (T)sc.eps;
     a.margin = (T)margin;
