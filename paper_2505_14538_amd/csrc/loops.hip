@@ -56,19 +56,6 @@ __device__ __forceinline__ double step_exp(double x) { return exp(x); }
 // particle, and return 1 when some h needs a wider staged set, 2 when an
 // iteration failed or some h has a support the box's early gradient/force
 // lists may not cover (0 otherwise).
-// A coordinate as a float bound: rounded down (up) when the value is a
-// double that float does not hold exactly, so a box stays around its points.
-__device__ __forceinline__ float float_down(float v) { return v; }
-__device__ __forceinline__ float float_up(float v) { return v; }
-__device__ __forceinline__ float float_down(double v) {
-    const float f = (float)v;
-    return (double)f > v ? nextafterf(f, -INFINITY) : f;
-}
-__device__ __forceinline__ float float_up(double v) {
-    const float f = (float)v;
-    return (double)f < v ? nextafterf(f, INFINITY) : f;
-}
-
 template <typename T, int CAP, bool SINGLE = false>
 __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T>& a, int t,
                                             WaveStats& ws, float Rset = 0.f) {
@@ -106,7 +93,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
     if (h < (T)0) h = -h;
     const bool fixed = (a.flags & SWSPH_FIXED_H) != 0;
     // a fix-up pass over the pending particles stages around their box only
-    // (recorded by the pass that flagged them; the task build used it too)
+    // (recorded by the fix-up task build, whose list serves that box)
     TileGeom g = geom_of(tl);
     if (selm && a.fbox) {
 #pragma unroll
@@ -487,32 +474,13 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
         const unsigned long long pmask = ballot(pend);
         const unsigned long long fmask = ballot(failed && js == 0);
         T wmax = 0;
-        float plo[3] = {0.f, 0.f, 0.f}, phi[3] = {0.f, 0.f, 0.f};
-        if (pmask) {
-            wmax = wave_max(pend ? want : (T)0);
-            // the box of the pending particles (the next pass searches and
-            // stages around it only), widened to float outward
-            const T big = (T)3.0e38f;
-            const T px[3] = {pi.x, pi.y, pi.z};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                plo[d] = float_down(wave_min(pend ? px[d] : big));
-                phi[d] = float_up(wave_max(pend ? px[d] : -big));
-            }
-        }
+        if (pmask) wmax = wave_max(pend ? want : (T)0);
         if (lane == 0) {
             if (pmask) {
                 T Rn = eps * wmax * (T)1.0625;
                 if (!(Rn < Rcap)) Rn = Rcap;
                 a.trad[t] = (float)Rn;
                 a.tflag[t] = 1;
-                if (a.fbox) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        a.fbox[6 * t + d] = plo[d];
-                        a.fbox[6 * t + 3 + d] = phi[d];
-                    }
-                }
             } else {
                 a.tflag[t] = 0;
             }

@@ -233,6 +233,19 @@ __device__ __forceinline__ double mul_unfused(double a, double b) {
     return a * b;
 }
 
+// A coordinate as a float bound: rounded down (up) when the value is a
+// double that float does not hold exactly, so a box stays around its points.
+__device__ __forceinline__ float float_down(float v) { return v; }
+__device__ __forceinline__ float float_up(float v) { return v; }
+__device__ __forceinline__ float float_down(double v) {
+    const float f = (float)v;
+    return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float float_up(double v) {
+    const float f = (float)v;
+    return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+
 __device__ __forceinline__ float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_sqrtf(x); }

@@ -30,7 +30,7 @@ struct TArgs {
     int64_t cand_cap;
     float* trad;
     const int32_t* tflag;
-    const float* fbox;  // density fix-ups: box of each flagged tile's pending particles
+    float* fbox;  // density fix-ups: box of each flagged tile's pending particles
     Counters* cnt;
     T eps;
     T margin;   // on the tile's radius eps * hmax
@@ -168,14 +168,24 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
     for (int d = 0; d < 3; ++d) { g.lo[d] = tl.lo[d]; g.hi[d] = tl.hi[d]; }
     if (MODE == 0 && fixup && a.fbox) {
         // a density fix-up iterates only the particles left pending (their
-        // h stored negated), inside the box the flagging pass recorded: the
-        // list serves that box (the loop culls with the same one)
+        // h stored negated): the list serves the box around them, which is
+        // recorded for the loop (it culls with the same box)
         const bool pend = lane < tl.count && a.hs[tl.begin + lane] < (T)0;
         if (ballot(pend) != 0ull) {
+            const V4<T> p = a.pos4[tl.begin + (pend ? lane : 0)];
+            const T big = (T)3.0e38f;
+            const T px[3] = {p.x, p.y, p.z};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                g.lo[d] = a.fbox[6 * t + d];
-                g.hi[d] = a.fbox[6 * t + 3 + d];
+                g.lo[d] = float_down(wave_min(pend ? px[d] : big));
+                g.hi[d] = float_up(wave_max(pend ? px[d] : -big));
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    a.fbox[6 * t + d] = g.lo[d];
+                    a.fbox[6 * t + 3 + d] = g.hi[d];
+                }
             }
         }
     }
