@@ -151,7 +151,8 @@ __device__ int64_t task_one(const TArgs<T>& a, TaskMem& m, TaskWindow& win, cons
         R = a.trad[t];
     } else {
         const bool act = lane < tl.count;
-        const T h = act ? a.hs[tl.begin + lane] : (T)0;
+        // (a density fix-up marks a pending h by its sign)
+        const T h = act ? fabs(a.hs[tl.begin + lane]) : (T)0;
         const T hmax = wave_max(h);
         // float radius rounded up so it still covers every support of the tile
         R = (float)(a.eps * hmax * a.margin * (T)(1 + 4e-7));
