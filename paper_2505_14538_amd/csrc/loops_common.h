@@ -598,6 +598,9 @@ template <typename T, class Run>
 __device__ __forceinline__ void for_each_task(const KArgs<T>& a, int mode, Run&& run) {
     const int wave = threadIdx.x / WAVE;
     const int64_t nt = (int64_t)*a.ntask;
+    // an empty task list (a density fix-up pass with nothing flagged) ends
+    // before any wavefront pops the shared counter
+    if (nt <= 0) return;
     const bool queue = mode == MODE_QUEUE;
     const int qc = a.qchunk > 0 ? a.qchunk : QCHUNK;
     const bool split = queue && a.xcd_split;

@@ -138,6 +138,21 @@ __device__ __forceinline__ int xcc_id() {
 // f(k) is called by the whole wavefront at one site.  Bounded: every
 // iteration takes one item or moves to the next segment.
 constexpr int NSEG = 8;
+
+// A pop that is not prefetched (a wavefront's first on a segment): `step`
+// more positions of the counter, or `limit` (the segment's length: drained)
+// without an atomic when a plain read already shows the counter there.  The
+// counter only grows, so that read cannot report a drained segment early; a
+// drained queue then costs each wavefront a load instead of a
+// read-modify-write on one shared address (thousands of those serialise: an
+// empty launch took tens of microseconds).  Lane 0 only.
+__device__ __forceinline__ int queue_pop_checked(unsigned long long* head, unsigned long long step,
+                                                 int64_t limit) {
+    const unsigned long long cur =
+        __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int64_t)cur >= limit) return (int)limit;
+    return (int)atomicAdd(head, step);
+}
 template <class F>
 __device__ __forceinline__ void for_each_item(unsigned long long* heads, int64_t n, bool split,
                                               F&& f) {
@@ -146,7 +161,7 @@ __device__ __forceinline__ void for_each_item(unsigned long long* heads, int64_t
     int y = 0, x = x0;
     int64_t b = split ? n * x / NSEG : 0, e = split ? n * (x + 1) / NSEG : n;
     int v = 0;
-    if (lane_id() == 0) v = (int)atomicAdd(&heads[x], 1ull);
+    if (lane_id() == 0) v = queue_pop_checked(&heads[x], 1ull, e - b);
     int64_t k = b + (int64_t)uniform(v);
     const int64_t guard_max = n + 2 * NSEG + 2;
     for (int64_t guard = 0; guard < guard_max; ++guard) {
@@ -156,7 +171,7 @@ __device__ __forceinline__ void for_each_item(unsigned long long* heads, int64_t
             b = n * x / NSEG;
             e = n * (x + 1) / NSEG;
             int w = 0;
-            if (lane_id() == 0) w = (int)atomicAdd(&heads[x], 1ull);
+            if (lane_id() == 0) w = queue_pop_checked(&heads[x], 1ull, e - b);
             k = b + (int64_t)uniform(w);
             continue;
         }
