@@ -877,21 +877,36 @@ static int launch_loop(KArgs<T> a, int mode, int lds_cap, int queue_slot, hipStr
 }
 
 // Indices of the tiles flagged for a density fix-up (any order: tiles are
-// independent), one atomic per wavefront.
+// independent).  Each wavefront owns FIX_RUNS consecutive runs of 64 tiles:
+// it counts their flags, takes its space with one atomic (only if any are
+// set) and writes them -- flagged tiles are few and scattered, so one atomic
+// per 64 tiles left hundreds of wavefronts queueing on the same counter.
+constexpr int FIX_RUNS = 16;
 __global__ void k_fix_list(const int32_t* __restrict__ tflag,
                            const unsigned long long* __restrict__ ntiles,
                            Counters* __restrict__ cnt, int32_t* __restrict__ list) {
     const int64_t nt = (int64_t)*ntiles;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nt; base += nth) {
-        const int64_t t = base + threadIdx.x;
-        const bool f = t < nt && tflag[t] != 0;
-        const unsigned long long m = ballot(f);
+    const int lane = lane_id();
+    const int64_t span = (int64_t)FIX_RUNS * WAVE;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (int64_t base = w * span; base < nt; base += nw * span) {
+        int tot = 0;
+        for (int r = 0; r < FIX_RUNS; ++r) {
+            const int64_t t = base + (int64_t)r * WAVE + lane;
+            tot += __popcll(ballot(t < nt && tflag[t] != 0));
+        }
+        if (tot == 0) continue;
         int at = 0;
-        if (lane_id() == 0 && m)
-            at = (int)atomicAdd(&cnt->n_fix, (unsigned long long)__popcll(m));
+        if (lane == 0) at = (int)atomicAdd(&cnt->n_fix, (unsigned long long)tot);
         at = __shfl(at, 0, WAVE);
-        if (f) list[at + mbcnt(m)] = (int32_t)t;
+        for (int r = 0; r < FIX_RUNS; ++r) {
+            const int64_t t = base + (int64_t)r * WAVE + lane;
+            const bool f = t < nt && tflag[t] != 0;
+            const unsigned long long m = ballot(f);
+            if (f) list[at + mbcnt(m)] = (int32_t)t;
+            at += __popcll(m);
+        }
     }
 }
 
@@ -910,7 +925,8 @@ static int density_fixups(const BinPtrs& b, const Scheme& sc, KArgs<T> a, int mo
     int r = 0;
     for (int pass = 1; pass <= DENS_FIXUPS && !r; ++pass) {
         launch_fill_u32(&b.cnt->n_fix, 2, 0u, s);
-        hipLaunchKernelGGL(k_fix_list, dim3(wave_grid(b.tile_cap, 4)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_fix_list, dim3(wave_grid((b.tile_cap + FIX_RUNS - 1) / FIX_RUNS, 4)),
+                           dim3(256), 0, s,
                            (const int32_t*)b.tflag, (const unsigned long long*)b.ntiles, b.cnt,
                            b.tmpidx);
         launch_tasks<T>(b, sc, 0, true, s);
