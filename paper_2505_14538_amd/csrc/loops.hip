@@ -234,7 +234,7 @@ __device__ __forceinline__ int density_tile(WaveMem<T, CAP, 1>& m, const KArgs<T
                 // next radius from the local h^3 scaling of G (a Newton step
                 // from below can overshoot far), grown at most 2x per pass
                 pend = true;
-                const T grow = (T)1.05 * cbrt(Tt / G);
+                const T grow = (T)1.02 * cbrt(Tt / G);
                 want = h * min((T)2, max((T)1.02, grow));
             }
         } else if (fabs(hn - h) <= tiny * h) {
